@@ -1,0 +1,275 @@
+/*
+ * FP64 CPU oracle for periodic tricubic B-spline orbital evaluation.
+ * TEST INFRASTRUCTURE ONLY: used by tests, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the GPU library.
+ *
+ * Every function follows the paper's definition directly, in the paper's
+ * order: locate the cell (Eq. SplineFunc: i = floor(x/Delta)), form the 1-D
+ * weights, then sum the 4x4x4 tensor product (Eq. TricubicValue).  There is
+ * no blocking or reordering beyond that definition.
+ *
+ * Readings of points the paper leaves open (each is also listed in the
+ * design notes):
+ *  - basis (paper Fig. 2 is missing): the uniform cubic B-spline, written
+ *    here as the centered function B(s) of de Boor's "Practical Guide to
+ *    Splines", so the term for coefficient i0-1+m at fraction t is
+ *    B(t+1-m);
+ *  - index offset: the sum runs over i0-1 .. i0+2 (Eq. SplineFunc), and the
+ *    unpadded table is periodic, so coefficient index (i0-1+m) mod n;
+ *  - box: orthorhombic, Delta_d = L_d/n_d; positions wrap periodically;
+ *  - derivatives are Cartesian (1/Delta, 1/Delta^2), Laplacian = trace H;
+ *  - Hessian keeps the 6 upper-triangle components xx,xy,xz,yy,yz,zz;
+ *  - outputs are overwritten, not accumulated into.
+ */
+#include "bspline_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+void oracle_basis(double s, double* b, double* db, double* d2b)
+{
+    double a = fabs(s);
+    double sg = (s < 0.0) ? -1.0 : 1.0;
+    if (a < 1.0) {
+        *b = 2.0 / 3.0 - a * a + 0.5 * a * a * a;
+        *db = sg * (-2.0 * a + 1.5 * a * a);
+        *d2b = -2.0 + 3.0 * a;
+    } else if (a < 2.0) {
+        double r = 2.0 - a;
+        *b = r * r * r / 6.0;
+        *db = -sg * 0.5 * r * r;
+        *d2b = r;
+    } else {
+        *b = 0.0;
+        *db = 0.0;
+        *d2b = 0.0;
+    }
+}
+
+void oracle_weights(double t, double delta, double w[4], double dw[4], double d2w[4])
+{
+    for (int m = 0; m < 4; ++m) {
+        double b, db, d2b;
+        oracle_basis(t + 1.0 - m, &b, &db, &d2b);
+        w[m] = b;
+        dw[m] = db / delta;
+        d2w[m] = d2b / (delta * delta);
+    }
+}
+
+int oracle_locate(double x, double box_len, int n, int* i0, double* t)
+{
+    double delta = box_len / n;
+    double u = x / delta;
+    if (!isfinite(u) || fabs(u) >= 1125899906842624.0 /* 2^50 */)
+        return -1;
+    /* periodic wrap into [0, n) */
+    u = u - n * floor(u / n);
+    if (u < 0.0)
+        u += n;
+    int i = (int)floor(u);
+    if (i >= n) { /* u rounded up to n: it is the image of 0 */
+        i = 0;
+        u = 0.0;
+    }
+    *i0 = i;
+    *t = u - i;
+    return 0;
+}
+
+static inline double coef_at(const void* coef, int dtype, int64_t idx)
+{
+    return dtype == ORACLE_COEF_F32 ? (double)((const float*)coef)[idx]
+                                    : ((const double*)coef)[idx];
+}
+
+static inline int wrap_index(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+static void fill_nan(int kind, int64_t p, int64_t ncoef, int64_t ldo,
+                     double* v, double* g, double* l, double* h)
+{
+    double q = NAN;
+    for (int64_t n = 0; n < ncoef; ++n) {
+        v[p * ldo + n] = q;
+        if (kind >= ORACLE_VGL)
+            for (int d = 0; d < 3; ++d) g[(p * 3 + d) * ldo + n] = q;
+        if (kind == ORACLE_VGL) l[p * ldo + n] = q;
+        if (kind == ORACLE_VGH)
+            for (int k = 0; k < 6; ++k) h[(p * 6 + k) * ldo + n] = q;
+    }
+}
+
+int oracle_eval(int kind, int nx, int ny, int nz, int64_t ncoef,
+                const void* coef, int coef_dtype, int padded,
+                const double box[3], int64_t npos, const double* pos,
+                double* v, double* g, double* l, double* h, int64_t ldo)
+{
+    if (kind < ORACLE_V || kind > ORACLE_VGH || nx <= 0 || ny <= 0 || nz <= 0 ||
+        ncoef <= 0 || npos < 0 || ldo < ncoef || !coef || (npos > 0 && (!pos || !v)))
+        return -1;
+    if (kind >= ORACLE_VGL && npos > 0 && !g) return -1;
+    if (kind == ORACLE_VGL && npos > 0 && !l) return -1;
+    if (kind == ORACLE_VGH && npos > 0 && !h) return -1;
+    const int dims[3] = {nx, ny, nz};
+    const double L[3] = {box ? box[0] : 1.0, box ? box[1] : 1.0, box ? box[2] : 1.0};
+    const int64_t sy = padded ? (int64_t)(nz + 3) : (int64_t)nz;
+    const int64_t sx = padded ? (int64_t)(ny + 3) * sy : (int64_t)ny * sy;
+    int status = 0;
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < npos; ++p) {
+        int i0[3];
+        double t[3], w[3][4], dw[3][4], d2w[3][4];
+        int bad = 0;
+        for (int d = 0; d < 3; ++d) {
+            double x = pos[d * npos + p];
+            if (!isfinite(x)) { bad = 1; break; }
+            if (oracle_locate(x, L[d], dims[d], &i0[d], &t[d]) != 0) { bad = 2; break; }
+            oracle_weights(t[d], L[d] / dims[d], w[d], dw[d], d2w[d]);
+        }
+        if (bad == 1) { fill_nan(kind, p, ncoef, ldo, v, g, l, h); continue; }
+        if (bad == 2) {
+#pragma omp atomic write
+            status = -1;
+            continue;
+        }
+
+        /* zero this position's outputs, then sum the 64 tensor-product terms */
+        for (int64_t n = 0; n < ncoef; ++n) {
+            v[p * ldo + n] = 0.0;
+            if (kind >= ORACLE_VGL)
+                for (int d = 0; d < 3; ++d) g[(p * 3 + d) * ldo + n] = 0.0;
+            if (kind == ORACLE_VGL) l[p * ldo + n] = 0.0;
+            if (kind == ORACLE_VGH)
+                for (int k = 0; k < 6; ++k) h[(p * 6 + k) * ldo + n] = 0.0;
+        }
+        for (int a = 0; a < 4; ++a) {
+            int ix = padded ? i0[0] + a : wrap_index(i0[0] - 1 + a, nx);
+            for (int b = 0; b < 4; ++b) {
+                int iy = padded ? i0[1] + b : wrap_index(i0[1] - 1 + b, ny);
+                for (int c = 0; c < 4; ++c) {
+                    int iz = padded ? i0[2] + c : wrap_index(i0[2] - 1 + c, nz);
+                    const int64_t row = ((int64_t)ix * sx + (int64_t)iy * sy + iz) * ncoef;
+                    /* weight of this term for each output component */
+                    const double wv = w[0][a] * w[1][b] * w[2][c];
+                    const double wgx = dw[0][a] * w[1][b] * w[2][c];
+                    const double wgy = w[0][a] * dw[1][b] * w[2][c];
+                    const double wgz = w[0][a] * w[1][b] * dw[2][c];
+                    const double whxx = d2w[0][a] * w[1][b] * w[2][c];
+                    const double whxy = dw[0][a] * dw[1][b] * w[2][c];
+                    const double whxz = dw[0][a] * w[1][b] * dw[2][c];
+                    const double whyy = w[0][a] * d2w[1][b] * w[2][c];
+                    const double whyz = w[0][a] * dw[1][b] * dw[2][c];
+                    const double whzz = w[0][a] * w[1][b] * d2w[2][c];
+                    for (int64_t n = 0; n < ncoef; ++n) {
+                        const double cf = coef_at(coef, coef_dtype, row + n);
+                        v[p * ldo + n] += wv * cf;
+                        if (kind >= ORACLE_VGL) {
+                            g[(p * 3 + 0) * ldo + n] += wgx * cf;
+                            g[(p * 3 + 1) * ldo + n] += wgy * cf;
+                            g[(p * 3 + 2) * ldo + n] += wgz * cf;
+                        }
+                        if (kind == ORACLE_VGL)
+                            l[p * ldo + n] += (whxx + whyy + whzz) * cf;
+                        if (kind == ORACLE_VGH) {
+                            h[(p * 6 + 0) * ldo + n] += whxx * cf;
+                            h[(p * 6 + 1) * ldo + n] += whxy * cf;
+                            h[(p * 6 + 2) * ldo + n] += whxz * cf;
+                            h[(p * 6 + 3) * ldo + n] += whyy * cf;
+                            h[(p * 6 + 4) * ldo + n] += whyz * cf;
+                            h[(p * 6 + 5) * ldo + n] += whzz * cf;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    return status;
+}
+
+/* Periodic sum of the basis over images: S(u, m) = sum_k B(u - m - k n). */
+static void image_sum(double u, int m, int n, double delta, double* s, double* ds, double* d2s)
+{
+    *s = *ds = *d2s = 0.0;
+    long kmin = (long)floor((u - m - 2.0) / n) - 1;
+    long kmax = (long)ceil((u - m + 2.0) / n) + 1;
+    for (long k = kmin; k <= kmax; ++k) {
+        double b, db, d2b;
+        oracle_basis(u - m - (double)k * n, &b, &db, &d2b);
+        *s += b;
+        *ds += db / delta;
+        *d2s += d2b / (delta * delta);
+    }
+}
+
+int oracle_eval_bruteforce(int nx, int ny, int nz, int64_t ncoef,
+                           const double* coef, const double box[3],
+                           int64_t npos, const double* pos,
+                           double* v, double* g, double* l, double* h, int64_t ldo)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0 || ncoef <= 0 || npos < 0 || ldo < ncoef || !coef)
+        return -1;
+    if (npos > 0 && (!pos || !v || !g || !l || !h)) return -1;
+    const int dims[3] = {nx, ny, nz};
+    const double L[3] = {box ? box[0] : 1.0, box ? box[1] : 1.0, box ? box[2] : 1.0};
+    int maxn = nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz);
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < npos; ++p) {
+        double* S = (double*)malloc(sizeof(double) * 9 * (size_t)maxn);
+        for (int d = 0; d < 3; ++d) {
+            double delta = L[d] / dims[d];
+            double u = pos[d * npos + p] / delta;
+            for (int m = 0; m < dims[d]; ++m)
+                image_sum(u, m, dims[d], delta, &S[(d * 3 + 0) * maxn + m],
+                          &S[(d * 3 + 1) * maxn + m], &S[(d * 3 + 2) * maxn + m]);
+        }
+#define SV(d, m) S[((d) * 3 + 0) * maxn + (m)]
+#define SD(d, m) S[((d) * 3 + 1) * maxn + (m)]
+#define SD2(d, m) S[((d) * 3 + 2) * maxn + (m)]
+        for (int64_t n = 0; n < ncoef; ++n) {
+            double acc[10] = {0};
+            for (int mx = 0; mx < nx; ++mx)
+                for (int my = 0; my < ny; ++my)
+                    for (int mz = 0; mz < nz; ++mz) {
+                        double c = coef[(((int64_t)mx * ny + my) * nz + mz) * ncoef + n];
+                        acc[0] += c * SV(0, mx) * SV(1, my) * SV(2, mz);
+                        acc[1] += c * SD(0, mx) * SV(1, my) * SV(2, mz);
+                        acc[2] += c * SV(0, mx) * SD(1, my) * SV(2, mz);
+                        acc[3] += c * SV(0, mx) * SV(1, my) * SD(2, mz);
+                        acc[4] += c * SD2(0, mx) * SV(1, my) * SV(2, mz);
+                        acc[5] += c * SD(0, mx) * SD(1, my) * SV(2, mz);
+                        acc[6] += c * SD(0, mx) * SV(1, my) * SD(2, mz);
+                        acc[7] += c * SV(0, mx) * SD2(1, my) * SV(2, mz);
+                        acc[8] += c * SV(0, mx) * SD(1, my) * SD(2, mz);
+                        acc[9] += c * SV(0, mx) * SV(1, my) * SD2(2, mz);
+                    }
+            v[p * ldo + n] = acc[0];
+            for (int d = 0; d < 3; ++d) g[(p * 3 + d) * ldo + n] = acc[1 + d];
+            for (int k = 0; k < 6; ++k) h[(p * 6 + k) * ldo + n] = acc[4 + k];
+            l[p * ldo + n] = acc[4] + acc[7] + acc[9];
+        }
+#undef SV
+#undef SD
+#undef SD2
+        free(S);
+    }
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
