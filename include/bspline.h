@@ -1,0 +1,220 @@
+/*
+ * bspline.h - C ABI of the MI355X (gfx950) tricubic B-spline orbital
+ * evaluator.
+ *
+ * The library evaluates N periodic tricubic B-spline orbitals at a batch of
+ * electron positions (paper: "QMC and B-spline-based SPOs", Eq. SplineFunc
+ * and Eq. TricubicValue; kernels V, VGL and VGH of section "Baseline and
+ * miniQMC", Fig. 4(b)).  For each position it finds the grid cell, forms the
+ * 4x4x4 cubic-basis weights and reduces the 64 coefficient rows of every
+ * spline into:
+ *   V   value                                   (1 output stream)
+ *   VGL value, gradient, Laplacian              (1 + 3 + 1 streams)
+ *   VGH value, gradient, symmetric Hessian      (1 + 3 + 6 streams)
+ * Output streams are structure-of-arrays (section "Optimizations and
+ * Parallelization", AoS-to-SoA subsection), one row of N per component.
+ *
+ * General conventions
+ *  - Every function returns a bspl_status; nothing throws across the ABI.
+ *    On failure spline_last_error() describes the cause (per thread).
+ *  - Streams are passed as `void*` holding a hipStream_t (NULL = the null
+ *    stream).  Evaluation is asynchronous and stream-ordered.
+ *  - The caller owns position and output buffers; the library owns table and
+ *    plan memory.  A table is immutable after creation and may be read by
+ *    evaluations on several streams at once.
+ *  - Positions are FP64 device arrays laid out [3][npos]: all x, then all y,
+ *    then all z.  They are wrapped periodically into the box, so any finite
+ *    position is valid.  A non-finite position yields NaN in every output of
+ *    that position and never an out-of-bounds read.  A finite position so
+ *    far out (|x/Delta| >= 2^50) that no fraction bits remain is evaluated at
+ *    some grid point of the table.
+ *  - Outputs are FP32 device arrays; element n of component c of position p
+ *    is out[(p*ncomp + c)*ldo + n] with ldo >= N.  Columns [0,N) are
+ *    overwritten (never accumulated into); columns [N,ldo) are not touched.
+ */
+#ifndef BSPLINE_H
+#define BSPLINE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BSPL_OK = 0,
+    BSPL_EINVAL = 1,       /* bad argument: NULL, non-positive size, bad enum */
+    BSPL_ENOMEM = 2,       /* device or host allocation failed */
+    BSPL_EDEVICE = 3,      /* a HIP call failed; see spline_last_error() */
+    BSPL_EUNSUPPORTED = 4, /* valid request this build does not support */
+    BSPL_EIO = 5           /* wisdom file could not be read or written */
+} bspl_status;
+
+/* Storage type of the coefficient table.  F16 and BF16 tables hold c/s_n
+ * rounded to nearest-even, with a per-spline FP32 scale s_n = 2^ceil(log2
+ * max|c_n|) (1 for an all-zero spline); evaluation converts to FP32,
+ * accumulates in FP32 and multiplies each output by s_n once.             */
+typedef enum { BSPL_F32 = 0, BSPL_F16 = 1, BSPL_BF16 = 2 } bspl_dtype;
+
+/* Which outputs to produce (paper Fig. 3: V, VGL, VGH). */
+typedef enum { BSPL_V = 0, BSPL_VGL = 1, BSPL_VGH = 2 } bspl_kind;
+
+/* spline_table_create flags */
+#define BSPL_COEFS_PADDED 0x1u /* coefs are [nx+3][ny+3][nz+3][N], used as-is */
+#define BSPL_COEFS_DEVICE 0x2u /* coefs is a device pointer (else host)     */
+
+typedef struct bspl_table bspl_table;
+typedef struct bspl_plan bspl_plan;
+
+/* Layout of a table in device memory.  The table is 4-D,
+ * [nx+3][ny+3][nz+3][n_padded]: one row of n_padded coefficients per padded
+ * grid point, n fastest, each row starting on a 128-byte boundary (paper:
+ * coefficient array P[Nx][Ny][Nz][N] with aligned, padded rows, section
+ * "Baseline and miniQMC").  Padded index i holds the periodic coefficient
+ * (i-1) mod n, so the 4 rows a cell needs are always i0..i0+3.            */
+typedef struct {
+    int32_t nx, ny, nz;       /* grid cells per dimension */
+    int32_t px, py, pz;       /* padded points per dimension (n + 3) */
+    int64_t n_splines;        /* N */
+    int64_t n_padded;         /* row length in elements (multiple of 128 B) */
+    int32_t dtype;            /* bspl_dtype */
+    int32_t elem_bytes;       /* 4 or 2 */
+    int64_t row_bytes;        /* n_padded * elem_bytes */
+    int64_t table_bytes;      /* px*py*pz*row_bytes */
+    double box[3];            /* orthorhombic box lengths */
+    const void* data;         /* device pointer to the table (read-only) */
+    const float* scales;      /* device pointer to n_padded scales, or NULL */
+} bspl_table_info;
+
+/* Work decomposition of one evaluation.  A wavefront (64 lanes) handles one
+ * position and 64*vw consecutive splines at a time ("spline tile", the GPU
+ * counterpart of the paper's AoSoA tile N_b, section "Optimizations and
+ * Parallelization").  A workgroup holds wx tiles of the same positions
+ * side by side and wy positions: wx*wy wavefronts, at most 16.  grid = 0
+ * launches one workgroup per (wx tiles x wy positions) block; grid > 0
+ * launches that many persistent workgroups that loop over the blocks.    */
+typedef struct {
+    int32_t vw;   /* splines per lane: 1, 2, 4 (F32) or 2, 4, 8 (F16/BF16) */
+    int32_t wx;   /* wavefronts per workgroup along splines */
+    int32_t wy;   /* wavefronts per workgroup along positions */
+    int32_t grid; /* persistent workgroups, or 0 */
+} bspl_tile;
+
+/* Human-readable name of a status code (static string). */
+const char* spline_status_string(bspl_status s);
+
+/* Description of the last failure on the calling thread (static per thread;
+ * empty string if none). */
+const char* spline_last_error(void);
+
+/* Host-only layout query: fills *out (data and scales set to NULL) for the
+ * given shape without touching the device.  EINVAL for non-positive sizes
+ * or a bad dtype; EUNSUPPORTED when a size overflows 64-bit byte counts or
+ * the 4x4x4 row block of one cell spans 4 GiB or more.                   */
+bspl_status spline_layout_query(int nx, int ny, int nz, int64_t n_splines,
+                                bspl_dtype dtype, bspl_table_info* out);
+
+/* Create a table from FP32 coefficients.
+ *  coefs: [nx][ny][nz][n_splines], n fastest, periodic (the coefficient of
+ *         grid point (i,j,k) for spline n), on the host, or on the device
+ *         with BSPL_COEFS_DEVICE; with BSPL_COEFS_PADDED the array is
+ *         [nx+3][ny+3][nz+3][n_splines] and padded index i is used for
+ *         cell i-1 directly (no periodic fill).
+ *  box:   three box lengths (> 0), or NULL for the unit cube.
+ *  The library copies, pads, converts and owns the table.  The call
+ *  returns when the table is ready on the device; coefs may be freed then.
+ *  Errors: EINVAL (NULL out/coefs, sizes <= 0, bad dtype, box <= 0),
+ *  ENOMEM, EDEVICE, EUNSUPPORTED (see spline_layout_query).               */
+bspl_status spline_table_create(bspl_table** out, int nx, int ny, int nz,
+                                int64_t n_splines, const float* coefs,
+                                bspl_dtype dtype, const double box[3],
+                                unsigned flags, void* stream);
+
+/* Free a table.  NULL is accepted.  No evaluation may still be in flight on
+ * it (hipFree semantics). */
+bspl_status spline_table_destroy(bspl_table* t);
+
+/* Describe a table (device pointers included). */
+bspl_status spline_table_info(const bspl_table* t, bspl_table_info* out);
+
+/* Value only (paper Fig. 3, V).  v: [npos][ldo]. */
+bspl_status spline_eval_v(const bspl_table* t, int64_t npos, const double* pos,
+                          float* v, int64_t ldo, void* stream);
+
+/* Value, gradient, Laplacian (paper Fig. 3, VGL).  v: [npos][ldo],
+ * g: [npos][3][ldo] (gx, gy, gz), l: [npos][ldo] (trace of the Hessian). */
+bspl_status spline_eval_vgl(const bspl_table* t, int64_t npos, const double* pos,
+                            float* v, float* g, float* l, int64_t ldo, void* stream);
+
+/* Value, gradient, Hessian (paper Fig. 4(b), VGH).  v: [npos][ldo],
+ * g: [npos][3][ldo], h: [npos][6][ldo] ordered xx, xy, xz, yy, yz, zz.     */
+bspl_status spline_eval_vgh(const bspl_table* t, int64_t npos, const double* pos,
+                            float* v, float* g, float* h, int64_t ldo, void* stream);
+
+/* Any kind with an explicit work decomposition (tile NULL = the tuned or
+ * default one).  lh is l for VGL and h for VGH; g and lh are ignored for V.
+ * EINVAL if the tile is not valid for the table's dtype.                   */
+bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos,
+                        const double* pos, float* v, float* g, float* lh,
+                        int64_t ldo, const bspl_tile* tile, void* stream);
+
+/* The decomposition spline_eval uses when given tile = NULL: the tuned one
+ * from the wisdom cache if it holds this shape, else a built-in default.   */
+bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos,
+                               bspl_tile* out);
+
+/* Autotuner (the paper tunes the tile size N_b once per machine by an
+ * exhaustive sweep and plans an FFTW-like "wisdom" file, section
+ * "Experiments and Results").  Times every valid decomposition on this
+ * table at this batch size with uniformly random positions, keeps the
+ * fastest in the in-process wisdom cache, appends it to wisdom_path when
+ * that is not NULL, and returns it in *best (may be NULL).  Allocates and
+ * frees its own scratch buffers; synchronizes the stream.                 */
+bspl_status spline_autotune(const bspl_table* t, bspl_kind kind, int64_t npos,
+                            const char* wisdom_path, bspl_tile* best, void* stream);
+
+/* Load wisdom entries from a file into the cache (EIO if unreadable). */
+bspl_status spline_wisdom_load(const char* path);
+
+/* Write the whole wisdom cache to a file (EIO on failure). */
+bspl_status spline_wisdom_save(const char* path);
+
+/* Batched evaluation of several tables in one persistent launch, replayed
+ * from a captured HIP graph (paper: independent AoSoA tiles and walkers,
+ * section "Optimizations and Parallelization", Fig. 6).  All tables must
+ * share one dtype.  npos[i] positions go to table i.  Buffers are bound at
+ * plan creation:
+ *   pos[i]   device [3][npos[i]] FP64
+ *   v[i]     device [npos[i]][ldo[i]]
+ *   g[i]     device [npos[i]][3][ldo[i]]           (VGL, VGH; else NULL)
+ *   lh[i]    device l or h as for spline_eval       (VGL, VGH; else NULL)
+ * tile: one decomposition for the whole launch, or NULL to autotune it at
+ * plan creation (consulting and extending wisdom_path when not NULL).
+ * Tables and buffers must outlive the plan.  At most 16 tables.           */
+bspl_status spline_batch_plan_create(bspl_plan** out, int ntables,
+                                     const bspl_table* const* tables,
+                                     const int64_t* npos, bspl_kind kind,
+                                     const double* const* pos, float* const* v,
+                                     float* const* g, float* const* lh,
+                                     const int64_t* ldo, const bspl_tile* tile,
+                                     const char* wisdom_path, void* stream);
+
+/* Replay the plan's graph on a stream.  Returns as soon as it is queued. */
+bspl_status spline_batch_execute(bspl_plan* p, void* stream);
+
+/* Rebind the buffers of table i in an existing plan (same npos and ldo
+ * rules); takes effect from the next execute.                             */
+bspl_status spline_batch_rebind(bspl_plan* p, int i, const double* pos, float* v,
+                                float* g, float* lh);
+
+/* The decomposition a plan launches with. */
+bspl_status spline_batch_plan_tile(const bspl_plan* p, bspl_tile* out);
+
+/* Free a plan (NULL accepted).  No replay may still be in flight. */
+bspl_status spline_batch_plan_destroy(bspl_plan* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSPLINE_H */

@@ -1,0 +1,313 @@
+// Autotuner and wisdom cache.
+//
+// The paper tunes the tile size N_b once per machine by sweeping powers of
+// two and plans an FFTW-like wisdom file for production runs (section
+// "Experiments and Results").  Here the sweep covers every valid work
+// decomposition (splines per lane, wavefronts per workgroup along splines
+// and positions, persistent grid size), timed with HIP events on the real
+// table at the real batch size; the winner is cached per
+// (arch, dtype, kind, N, grid, npos bucket) and can be written to a text file.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace bspl {
+
+namespace {
+
+std::mutex g_mu;
+std::map<std::string, bspl_tile>& cache() {
+    static std::map<std::string, bspl_tile> c;
+    return c;
+}
+
+// gfx architecture of the current device, without feature suffixes; looked
+// up once per device.
+std::string arch_name() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    a = c == std::string::npos ? a : a.substr(0, c);
+    names[dev] = a;
+    return a;
+}
+
+int64_t pow2_bucket(int64_t n) {
+    int64_t b = 1;
+    while (b < n) b <<= 1;
+    return b;
+}
+
+bool parse_line(const char* line, std::string* key, bspl_tile* t) {
+    char k[256];
+    bspl_tile x{};
+    if (sscanf(line, "%255s %d %d %d %d", k, &x.vw, &x.wx, &x.wy, &x.grid) != 5) return false;
+    *key = k;
+    *t = x;
+    return true;
+}
+
+// Uniform random positions in the box: a counter hash per coordinate.
+__global__ void random_positions(double* pos, int64_t npos, double lx, double ly, double lz,
+                                 uint64_t salt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * npos) return;
+    uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + salt;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    const int64_t d = i / npos;
+    pos[i] = u * (d == 0 ? lx : (d == 1 ? ly : lz));
+}
+
+}  // namespace
+
+void wisdom_key(char* buf, size_t n, int dtype, int kind, int64_t nsplines, const int32_t nc[3],
+                int64_t npos, const char* prefix) {
+    static const char* dt[] = {"f32", "f16", "bf16"};
+    static const char* kd[] = {"v", "vgl", "vgh"};
+    snprintf(buf, n, "%s|%s|%s|%s|N%lld|%dx%dx%d|p%lld", prefix, arch_name().c_str(),
+             dt[dtype], kd[kind], (long long)nsplines, nc[0], nc[1], nc[2],
+             (long long)pow2_bucket(npos));
+}
+
+bool wisdom_lookup(const char* key, bspl_tile* out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = cache().find(key);
+    if (it == cache().end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void wisdom_store(const char* key, const bspl_tile& tile) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    cache()[key] = tile;
+}
+
+// Candidate decompositions for a table (and, for batched launches, grid
+// sizes as multiples of the compute-unit count).
+std::vector<bspl_tile> tile_candidates(int dtype, int64_t max_nsplines, bool persistent) {
+    std::vector<bspl_tile> out;
+    const int vws32[] = {1, 2, 4}, vws16[] = {2, 4, 8};
+    const int* vws = dtype == BSPL_F32 ? vws32 : vws16;
+    const int shapes[][2] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {1, 2}, {1, 4},
+                             {2, 2}, {4, 2}, {2, 4}, {1, 8}};
+    const int cus = device_cu_count();
+    const int grids_p[] = {0, 1, 2, 4, 8};
+    const int grids_s[] = {0};
+    for (int vi = 0; vi < 3; ++vi) {
+        const int vw = vws[vi];
+        const int64_t chunks = (max_nsplines + 64 * vw - 1) / (64 * vw);
+        if (vi > 0 && chunks * 64 * vw > 2 * max_nsplines && chunks == 1) continue;
+        for (auto& s : shapes) {
+            if (s[0] > chunks && s[0] > 1) continue;
+            const int* grids = persistent ? grids_p : grids_s;
+            const int ng = persistent ? 5 : 1;
+            for (int gi = 0; gi < ng; ++gi) {
+                bspl_tile t{vw, s[0], s[1], grids[gi] * cus};
+                out.push_back(t);
+            }
+        }
+    }
+    return out;
+}
+
+// Time `launch` (already bound to its buffers) with events: median of runs.
+template <typename F>
+static bspl_status time_launch(F&& launch, hipStream_t s, int reps, float* us) {
+    hipEvent_t a, b;
+    BSPL_HIP(hipEventCreate(&a));
+    BSPL_HIP(hipEventCreate(&b));
+    for (int w = 0; w < 2; ++w) {
+        bspl_status st = launch(w);
+        if (st != BSPL_OK) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return st;
+        }
+    }
+    std::vector<float> t;
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(a, s);
+        bspl_status st = launch(r);
+        (void)hipEventRecord(b, s);
+        hipError_t e = hipEventSynchronize(b);
+        if (st != BSPL_OK || e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return st != BSPL_OK ? st : hip_fail(e, "autotune timing");
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms * 1000.f);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    std::sort(t.begin(), t.end());
+    *us = t[t.size() / 2];
+    return BSPL_OK;
+}
+
+bspl_status fill_random_positions(double* pos, int64_t npos, const double box[3], uint64_t salt,
+                                  hipStream_t s) {
+    if (npos <= 0) return BSPL_OK;
+    const int64_t n = 3 * npos;
+    hipLaunchKernelGGL(random_positions, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos,
+                       npos, box[0], box[1], box[2], salt);
+    BSPL_HIP(hipGetLastError());
+    return BSPL_OK;
+}
+
+// Sweep tiles for a launch described by `run(tile, iteration)`.
+bspl_status sweep(const std::vector<bspl_tile>& cands, hipStream_t s,
+                  bspl_status (*run)(void*, const bspl_tile&, int), void* ctx, bspl_tile* best,
+                  float* best_us) {
+    bool have = false;
+    for (const bspl_tile& t : cands) {
+        float us = 0;
+        auto call = [&](int it) { return run(ctx, t, it); };
+        bspl_status st = time_launch(call, s, 5, &us);
+        if (st != BSPL_OK) return st;
+        if (!have || us < *best_us) {
+            *best = t;
+            *best_us = us;
+            have = true;
+        }
+    }
+    return have ? BSPL_OK : fail(BSPL_EUNSUPPORTED, "no candidate tile");
+}
+
+static bspl_status append_wisdom(const char* path, const char* key, const bspl_tile& t,
+                                 float us) {
+    FILE* f = fopen(path, "a");
+    if (!f) return fail(BSPL_EIO, "cannot append to wisdom file %s", path);
+    fprintf(f, "%s %d %d %d %d %.3f\n", key, t.vw, t.wx, t.wy, t.grid, us);
+    const bool ok = fclose(f) == 0;
+    return ok ? BSPL_OK : fail(BSPL_EIO, "cannot write wisdom file %s", path);
+}
+
+bspl_status record_wisdom(const char* path, const char* key, const bspl_tile& t, float us) {
+    wisdom_store(key, t);
+    return path ? append_wisdom(path, key, t, us) : BSPL_OK;
+}
+
+}  // namespace bspl
+
+using namespace bspl;
+
+namespace {
+
+struct SingleCtx {
+    const bspl_table* t;
+    int kind;
+    int64_t npos;
+    double* pos[4];
+    float* out[3];
+    int64_t ldo;
+    hipStream_t s;
+};
+
+bspl_status run_single(void* vctx, const bspl_tile& tile, int it) {
+    SingleCtx* c = static_cast<SingleCtx*>(vctx);
+    TableDesc d;
+    bspl_status st = make_desc(c->t, c->npos, c->pos[it & 3], c->out[0], c->out[1], c->out[2],
+                               c->ldo, tile.vw, tile.wx, tile.wy, &d);
+    if (st != BSPL_OK) return st;
+    return launch_single(c->t, c->kind, d, tile, c->s);
+}
+
+}  // namespace
+
+extern "C" {
+
+bspl_status spline_autotune(const bspl_table* t, bspl_kind kind, int64_t npos,
+                            const char* wisdom_path, bspl_tile* best, void* stream) {
+    if (!t) return fail(BSPL_EINVAL, "table is NULL");
+    if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
+    if (npos <= 0 || npos > INT32_MAX) return fail(BSPL_EINVAL, "npos %lld", (long long)npos);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int ncomp = kind == BSPL_V ? 1 : (kind == BSPL_VGL ? 5 : 10);
+    SingleCtx c{};
+    c.t = t;
+    c.kind = kind;
+    c.npos = npos;
+    c.ldo = t->info.n_padded;
+    c.s = s;
+    bspl_status st = BSPL_OK;
+    void* mem = nullptr;
+    const size_t pos_bytes = sizeof(double) * 3 * (size_t)npos;
+    const size_t out_bytes = sizeof(float) * (size_t)npos * (size_t)c.ldo;
+    const size_t total = 4 * pos_bytes + (size_t)ncomp * out_bytes + 4096;
+    hipError_t e = hipMalloc(&mem, total);
+    if (e != hipSuccess) return hip_fail(e, "autotune scratch");
+    char* m = static_cast<char*>(mem);
+    for (int b = 0; b < 4; ++b) {
+        c.pos[b] = reinterpret_cast<double*>(m);
+        m += (pos_bytes + 255) / 256 * 256;
+    }
+    c.out[0] = reinterpret_cast<float*>(m);
+    c.out[1] = c.out[0] + (size_t)npos * c.ldo;
+    c.out[2] = c.out[1] + (size_t)3 * npos * c.ldo;
+    for (int b = 0; b < 4 && st == BSPL_OK; ++b)
+        st = fill_random_positions(c.pos[b], npos, t->info.box, 0x5eed0000ull + b, s);
+    bspl_tile bt{};
+    float us = 0;
+    if (st == BSPL_OK) {
+        auto cands = tile_candidates(t->info.dtype, t->info.n_splines, false);
+        st = sweep(cands, s, run_single, &c, &bt, &us);
+    }
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(mem);
+    if (st != BSPL_OK) return st;
+    char key[256];
+    const int32_t nc[3] = {t->info.nx, t->info.ny, t->info.nz};
+    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos, "single");
+    st = record_wisdom(wisdom_path, key, bt, us);
+    if (best) *best = bt;
+    return st;
+}
+
+bspl_status spline_wisdom_load(const char* path) {
+    if (!path) return fail(BSPL_EINVAL, "path is NULL");
+    FILE* f = fopen(path, "r");
+    if (!f) return fail(BSPL_EIO, "cannot open wisdom file %s", path);
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        std::string key;
+        bspl_tile tile;
+        if (line[0] == '#' || !parse_line(line, &key, &tile)) continue;
+        wisdom_store(key.c_str(), tile);
+    }
+    fclose(f);
+    return BSPL_OK;
+}
+
+bspl_status spline_wisdom_save(const char* path) {
+    if (!path) return fail(BSPL_EINVAL, "path is NULL");
+    FILE* f = fopen(path, "w");
+    if (!f) return fail(BSPL_EIO, "cannot create wisdom file %s", path);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        for (auto& kv : cache())
+            fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.vw, kv.second.wx,
+                    kv.second.wy, kv.second.grid);
+    }
+    return fclose(f) == 0 ? BSPL_OK : fail(BSPL_EIO, "cannot write wisdom file %s", path);
+}
+
+}  // extern "C"

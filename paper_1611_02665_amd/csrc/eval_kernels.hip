@@ -1,0 +1,465 @@
+// Evaluation kernels for gfx950: V, VGL and VGH of periodic tricubic
+// B-splines (paper Eq. TricubicValue; kernels of Fig. 3 and Fig. 4(b)).
+//
+// Work unit: one wavefront, one position, one spline tile of 64*VW
+// consecutive splines.  Lane l owns splines [tile*64*VW + l*VW, +VW).
+//  1. Lanes 0..2 place the position in its cell, one dimension each, in FP64
+//     (periodic wrap, lower-bound index, fraction t rounded to FP32).
+//  2. Lanes 0..35 each form one of the 36 basis weights (value, first and
+//     second derivative, 4 per dimension, derivatives already scaled by
+//     1/Delta and 1/Delta^2); v_readlane broadcasts them into scalar
+//     registers, so every lane of the wavefront shares them for free.
+//  3. For each of the 16 (i,j) pairs the 4 z-consecutive rows of the tile
+//     are one coalesced load per row (16 bytes per lane at VW=4/FP32), and
+//     the reduction runs z first, then y, then x, all in FP32 registers.
+//  4. The 1, 5 or 10 output rows are written once, SoA.
+// The path is HBM-bound (about 2 flop/byte), so there is no MFMA and no LDS:
+// every byte moves once from HBM to registers.
+#include <type_traits>
+
+#include "internal.hpp"
+
+namespace bspl {
+namespace {
+
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct F32 {};
+struct F16 {};
+struct BF16 {};
+
+template <typename T> struct Elem;
+template <> struct Elem<F32> { static constexpr int bytes = 4; };
+template <> struct Elem<F16> { static constexpr int bytes = 2; };
+template <> struct Elem<BF16> { static constexpr int bytes = 2; };
+
+// Raw load of VW consecutive coefficients (one 4/8/16-byte access per lane)
+// and its widening to FP32.  Loads and widening are separate so that loads
+// can be issued several row groups ahead of the arithmetic.
+template <typename T, int VW> struct Row;
+
+template <int VW> struct Row<F32, VW> {
+    using raw = typename std::conditional<VW == 4, float4,
+                typename std::conditional<VW == 2, float2, float>::type>::type;
+    static __device__ __forceinline__ raw load(const char* p) {
+        return *reinterpret_cast<const raw*>(p);
+    }
+    static __device__ __forceinline__ void widen(const raw& q, float (&o)[VW]) {
+        if constexpr (VW == 4) {
+            o[0] = q.x; o[1] = q.y; o[2] = q.z; o[3] = q.w;
+        } else if constexpr (VW == 2) {
+            o[0] = q.x; o[1] = q.y;
+        } else {
+            o[0] = q;
+        }
+    }
+};
+
+template <int VW> struct Row<F16, VW> {
+    using raw = typename std::conditional<VW == 8, f16x8,
+                typename std::conditional<VW == 4, f16x4, f16x2>::type>::type;
+    static __device__ __forceinline__ raw load(const char* p) {
+        return *reinterpret_cast<const raw*>(p);
+    }
+    static __device__ __forceinline__ void widen(const raw& q, float (&o)[VW]) {
+#pragma unroll
+        for (int e = 0; e < VW; ++e) o[e] = (float)q[e];
+    }
+};
+
+__device__ __forceinline__ void bf16_pair(uint32_t w, float& lo, float& hi) {
+    lo = __uint_as_float(w << 16);
+    hi = __uint_as_float(w & 0xffff0000u);
+}
+
+template <int VW> struct Row<BF16, VW> {
+    using raw = typename std::conditional<VW == 8, u32x4,
+                typename std::conditional<VW == 4, u32x2, uint32_t>::type>::type;
+    static __device__ __forceinline__ raw load(const char* p) {
+        return *reinterpret_cast<const raw*>(p);
+    }
+    static __device__ __forceinline__ void widen(const raw& q, float (&o)[VW]) {
+        if constexpr (VW == 8) {
+            bf16_pair(q[0], o[0], o[1]); bf16_pair(q[1], o[2], o[3]);
+            bf16_pair(q[2], o[4], o[5]); bf16_pair(q[3], o[6], o[7]);
+        } else if constexpr (VW == 4) {
+            bf16_pair(q[0], o[0], o[1]); bf16_pair(q[1], o[2], o[3]);
+        } else {
+            bf16_pair(q, o[0], o[1]);
+        }
+    }
+};
+
+template <int VW>
+__device__ __forceinline__ void store_row(float* dst, const float (&x)[VW], int valid,
+                                          bool vec) {
+    if (vec && valid >= VW) {
+        if constexpr (VW == 4) {
+            *reinterpret_cast<float4*>(dst) = make_float4(x[0], x[1], x[2], x[3]);
+        } else if constexpr (VW == 2) {
+            *reinterpret_cast<float2*>(dst) = make_float2(x[0], x[1]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) dst[e] = x[e];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+            if (e < valid) dst[e] = x[e];
+    }
+}
+
+__device__ __forceinline__ float bcast(float x, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+// Basis weight number r (0..11) of a dimension at fraction t: r/4 selects
+// value, first or second derivative, r%4 the cell offset m.  These are the
+// uniform cubic B-spline pieces written as cubics in t (Horner form):
+//   m=0: (1-t)^3/6   m=1: (3t^3-6t^2+4)/6   m=2: (-3t^3+3t^2+3t+1)/6   m=3: t^3/6
+__device__ __forceinline__ float basis_weight(int r, float t) {
+    float c0, c1, c2, c3;
+    switch (r) {
+    case 0: c0 = 1.f / 6; c1 = -0.5f; c2 = 0.5f; c3 = -1.f / 6; break;
+    case 1: c0 = 2.f / 3; c1 = 0.f; c2 = -1.f; c3 = 0.5f; break;
+    case 2: c0 = 1.f / 6; c1 = 0.5f; c2 = 0.5f; c3 = -0.5f; break;
+    case 3: c0 = 0.f; c1 = 0.f; c2 = 0.f; c3 = 1.f / 6; break;
+    case 4: c0 = -0.5f; c1 = 1.f; c2 = -0.5f; c3 = 0.f; break;
+    case 5: c0 = 0.f; c1 = -2.f; c2 = 1.5f; c3 = 0.f; break;
+    case 6: c0 = 0.5f; c1 = 1.f; c2 = -1.5f; c3 = 0.f; break;
+    case 7: c0 = 0.f; c1 = 0.f; c2 = 0.5f; c3 = 0.f; break;
+    case 8: c0 = 1.f; c1 = -1.f; c2 = 0.f; c3 = 0.f; break;
+    case 9: c0 = -2.f; c1 = 3.f; c2 = 0.f; c3 = 0.f; break;
+    case 10: c0 = 1.f; c1 = -3.f; c2 = 0.f; c3 = 0.f; break;
+    default: c0 = 0.f; c1 = 1.f; c2 = 0.f; c3 = 0.f; break;
+    }
+    return ((c3 * t + c2) * t + c1) * t + c0;
+}
+
+// Cell location of one coordinate in FP64.  Returns false for a non-finite
+// input.  A position with no fraction bits left (|u| >= 2^50) is placed on
+// grid point 0.
+__device__ __forceinline__ bool locate(double x, double inv_delta, int n, int& i0, float& t) {
+    const double u = x * inv_delta;
+    if (!__builtin_isfinite(u)) {
+        i0 = 0;
+        t = 0.f;
+        return false;
+    }
+    const double nd = (double)n;
+    double w = 0.0;
+    if (__builtin_fabs(u) < 1125899906842624.0) {
+        w = u - nd * __builtin_floor(u / nd);
+        if (w < 0.0) w += nd;
+        if (w >= nd) w = 0.0;  // rounded up to n: the image of 0
+    }
+    int i = (int)__builtin_floor(w);
+    i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
+    i0 = i;
+    t = (float)(w - (double)i);
+    return true;
+}
+
+template <int KIND> struct Shape;
+template <> struct Shape<BSPL_V> { static constexpr int nout = 1, ny = 1; };
+template <> struct Shape<BSPL_VGL> { static constexpr int nout = 5, ny = 5; };
+template <> struct Shape<BSPL_VGH> { static constexpr int nout = 10, ny = 6; };
+
+// Row groups in flight per wavefront: 128 bytes of loads per lane (32 VGPRs).
+template <typename T, int VW> struct Depth {
+    static constexpr int value = 32 / (VW * Elem<T>::bytes) < 2 ? 2 : 32 / (VW * Elem<T>::bytes);
+};
+
+template <typename T, int VW, int KIND, int DEPTH = Depth<T, VW>::value>
+__device__ __forceinline__ void eval_unit(const TableDesc& d, int p, int chunk, int lane) {
+    constexpr int EB = Elem<T>::bytes;
+    constexpr int NOUT = Shape<KIND>::nout;
+    constexpr int NY = Shape<KIND>::ny;
+
+    // 1. cell index and fraction: lane d handles dimension d
+    int my_i0 = 0;
+    float my_t = 0.f;
+    int my_bad = 0;
+    if (lane < 3) {
+        const double x = d.pos[(int64_t)lane * d.npos + p];
+        const double invd = lane == 0 ? d.inv_delta[0] : (lane == 1 ? d.inv_delta[1] : d.inv_delta[2]);
+        const int n = lane == 0 ? d.ncell[0] : (lane == 1 ? d.ncell[1] : d.ncell[2]);
+        my_bad = locate(x, invd, n, my_i0, my_t) ? 0 : 1;
+    }
+    const int i0 = __builtin_amdgcn_readlane(my_i0, 0);
+    const int j0 = __builtin_amdgcn_readlane(my_i0, 1);
+    const int k0 = __builtin_amdgcn_readlane(my_i0, 2);
+    const int bad = __builtin_amdgcn_readlane(my_bad, 0) | __builtin_amdgcn_readlane(my_bad, 1) |
+                    __builtin_amdgcn_readlane(my_bad, 2);
+
+    // 2. weights: lane 12*dim + r computes weight r of that dimension
+    float wv;
+    {
+        const float tx = bcast(my_t, 0), ty = bcast(my_t, 1), tz = bcast(my_t, 2);
+        const int dim = lane >= 24 ? 2 : (lane >= 12 ? 1 : 0);
+        const int r = lane - 12 * dim;
+        const float t = dim == 0 ? tx : (dim == 1 ? ty : tz);
+        const float s = dim == 0 ? d.inv_delta_f[0] : (dim == 1 ? d.inv_delta_f[1] : d.inv_delta_f[2]);
+        wv = basis_weight(r, t);
+        wv *= r >= 8 ? s * s : (r >= 4 ? s : 1.f);
+        if (bad) wv = __builtin_nanf("");
+    }
+    float ax[4], dax[4], d2ax[4], ay[4], day[4], d2ay[4], az[4], daz[4], d2az[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        ax[m] = bcast(wv, m);
+        ay[m] = bcast(wv, 12 + m);
+        az[m] = bcast(wv, 24 + m);
+        if constexpr (KIND != BSPL_V) {
+            dax[m] = bcast(wv, 4 + m);
+            d2ax[m] = bcast(wv, 8 + m);
+            day[m] = bcast(wv, 16 + m);
+            d2ay[m] = bcast(wv, 20 + m);
+            daz[m] = bcast(wv, 28 + m);
+            d2az[m] = bcast(wv, 32 + m);
+        }
+    }
+
+    // 3. gather and reduce
+    const int n0 = chunk * (64 * VW) + lane * VW;
+    const int valid = d.nsplines - n0;  // > 0 for lanes that own splines
+    const char* base = d.table + (size_t)i0 * d.xstride + (size_t)j0 * d.ystride +
+                       (size_t)k0 * d.row_bytes + (size_t)chunk * (64 * VW * EB);
+    const uint32_t loff = valid > 0 ? (uint32_t)(lane * VW * EB) : 0u;
+
+    // Row groups g = 4i + j (16 of them, 4 z-rows each) stream through a ring
+    // of DEPTH groups: group g+DEPTH-1 is issued before group g is reduced,
+    // so DEPTH groups of loads are in flight per wavefront while register use
+    // stays bounded.  An empty asm that reads the partial sums of group g and
+    // clobbers memory orders "reduce g" before "issue g+DEPTH"; without it the
+    // compiler hoists all 64 loads to the top and spills.
+    using RowT = Row<T, VW>;
+    typename RowT::raw ring[DEPTH][4];
+    auto issue = [&](int g, int slot) {
+        const uint32_t go = loff + (uint32_t)(g >> 2) * d.xstride + (uint32_t)(g & 3) * d.ystride;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) ring[slot][k] = RowT::load(base + (go + (uint32_t)k * d.row_bytes));
+    };
+
+    float acc[NOUT][VW];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[o][e] = 0.f;
+    float Y[NY][VW];
+
+#pragma unroll
+    for (int g = 0; g < DEPTH - 1; ++g) issue(g, g);
+
+#pragma unroll
+    for (int g = 0; g < 16; ++g) {
+        if (g + DEPTH - 1 < 16) issue(g + DEPTH - 1, (g + DEPTH - 1) % DEPTH);
+        const int i = g >> 2, j = g & 3;
+        if (j == 0) {
+#pragma unroll
+            for (int o = 0; o < NY; ++o)
+#pragma unroll
+                for (int e = 0; e < VW; ++e) Y[o][e] = 0.f;
+        }
+        float q[4][VW];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) RowT::widen(ring[g % DEPTH][k], q[k]);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            float s0 = az[0] * q[0][e];
+            s0 = fmaf(az[1], q[1][e], s0);
+            s0 = fmaf(az[2], q[2][e], s0);
+            s0 = fmaf(az[3], q[3][e], s0);
+            Y[0][e] = fmaf(ay[j], s0, Y[0][e]);
+            if constexpr (KIND != BSPL_V) {
+                float s1 = daz[0] * q[0][e];
+                s1 = fmaf(daz[1], q[1][e], s1);
+                s1 = fmaf(daz[2], q[2][e], s1);
+                s1 = fmaf(daz[3], q[3][e], s1);
+                float s2 = d2az[0] * q[0][e];
+                s2 = fmaf(d2az[1], q[1][e], s2);
+                s2 = fmaf(d2az[2], q[2][e], s2);
+                s2 = fmaf(d2az[3], q[3][e], s2);
+                Y[1][e] = fmaf(day[j], s0, Y[1][e]);   // d/dy
+                Y[2][e] = fmaf(d2ay[j], s0, Y[2][e]);  // d2/dy2
+                Y[3][e] = fmaf(ay[j], s1, Y[3][e]);    // d/dz
+                if constexpr (KIND == BSPL_VGH) {
+                    Y[4][e] = fmaf(day[j], s1, Y[4][e]);  // d2/dydz
+                    Y[5][e] = fmaf(ay[j], s2, Y[5][e]);   // d2/dz2
+                } else {
+                    Y[4][e] = fmaf(ay[j], s2, Y[4][e]);   // d2/dz2
+                }
+            }
+        }
+        if (j == 3) {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                acc[0][e] = fmaf(ax[i], Y[0][e], acc[0][e]);  // v
+                if constexpr (KIND == BSPL_VGL) {
+                    acc[1][e] = fmaf(dax[i], Y[0][e], acc[1][e]);  // gx
+                    acc[2][e] = fmaf(ax[i], Y[1][e], acc[2][e]);   // gy
+                    acc[3][e] = fmaf(ax[i], Y[3][e], acc[3][e]);   // gz
+                    acc[4][e] = fmaf(d2ax[i], Y[0][e], acc[4][e]); // lap: xx
+                    acc[4][e] = fmaf(ax[i], Y[2][e] + Y[4][e], acc[4][e]);  // + yy + zz
+                }
+                if constexpr (KIND == BSPL_VGH) {
+                    acc[1][e] = fmaf(dax[i], Y[0][e], acc[1][e]);  // gx
+                    acc[2][e] = fmaf(ax[i], Y[1][e], acc[2][e]);   // gy
+                    acc[3][e] = fmaf(ax[i], Y[3][e], acc[3][e]);   // gz
+                    acc[4][e] = fmaf(d2ax[i], Y[0][e], acc[4][e]); // hxx
+                    acc[5][e] = fmaf(dax[i], Y[1][e], acc[5][e]);  // hxy
+                    acc[6][e] = fmaf(dax[i], Y[3][e], acc[6][e]);  // hxz
+                    acc[7][e] = fmaf(ax[i], Y[2][e], acc[7][e]);   // hyy
+                    acc[8][e] = fmaf(ax[i], Y[4][e], acc[8][e]);   // hyz
+                    acc[9][e] = fmaf(ax[i], Y[5][e], acc[9][e]);   // hzz
+                }
+            }
+        }
+        if (g + DEPTH < 16) {
+            if (j == 3) {
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) asm volatile("" : "+v"(acc[o][e]));
+            } else {
+#pragma unroll
+                for (int o = 0; o < NY; ++o)
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) asm volatile("" : "+v"(Y[o][e]));
+            }
+            asm volatile("" ::: "memory");
+        }
+    }
+
+    // 4. scale (reduced-precision tables) and write
+    if (valid <= 0) return;
+    if constexpr (Elem<T>::bytes == 2) {
+        float sc[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) sc[e] = d.scales[n0 + e];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[o][e] *= sc[e];
+    }
+    const bool vec = d.vec_store != 0;
+    const int64_t ldo = d.ldo;
+    store_row<VW>(d.v + (int64_t)p * ldo + n0, acc[0], valid, vec);
+    if constexpr (KIND != BSPL_V) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            store_row<VW>(d.g + ((int64_t)p * 3 + c) * ldo + n0, acc[1 + c], valid, vec);
+    }
+    if constexpr (KIND == BSPL_VGL)
+        store_row<VW>(d.lh + (int64_t)p * ldo + n0, acc[4], valid, vec);
+    if constexpr (KIND == BSPL_VGH) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            store_row<VW>(d.lh + ((int64_t)p * 6 + c) * ldo + n0, acc[4 + c], valid, vec);
+    }
+}
+
+// One launch over one or several tables.  Workgroup-block g covers wx
+// spline tiles by wy positions of one table; blocks are numbered table by
+// table, positions outer, tiles inner.  With fewer workgroups than blocks
+// (persistent launch) each workgroup strides over the blocks.
+template <typename T, int VW, int KIND, int MAXT>
+__global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wxi = wave % a.wx;
+    const int wyi = wave / a.wx;
+    for (int64_t g = blockIdx.x; g < a.total_groups; g += gridDim.x) {
+        int ti = 0;
+        if constexpr (MAXT > 1) {
+            for (int k = 1; k < a.ntables; ++k)
+                if (g >= a.t[k].groups_begin) ti = k;
+        }
+        const TableDesc& d = a.t[ti];
+        const int local = (int)(g - d.groups_begin);
+        const int pg = local / d.xgroups;
+        const int cg = local - pg * d.xgroups;
+        const int chunk = cg * a.wx + wxi;
+        const int p = pg * a.wy + wyi;
+        if (chunk < d.nchunks && p < d.npos) eval_unit<T, VW, KIND>(d, p, chunk, lane);
+    }
+}
+
+template <typename T, int KIND, int MAXT>
+const void* pick_kernel(int vw) {
+    if constexpr (Elem<T>::bytes == 4) {
+        switch (vw) {
+        case 1: return (const void*)&eval_kernel<T, 1, KIND, MAXT>;
+        case 2: return (const void*)&eval_kernel<T, 2, KIND, MAXT>;
+        case 4: return (const void*)&eval_kernel<T, 4, KIND, MAXT>;
+        }
+    } else {
+        switch (vw) {
+        case 2: return (const void*)&eval_kernel<T, 2, KIND, MAXT>;
+        case 4: return (const void*)&eval_kernel<T, 4, KIND, MAXT>;
+        case 8: return (const void*)&eval_kernel<T, 8, KIND, MAXT>;
+        }
+    }
+    return nullptr;
+}
+
+template <int MAXT>
+const void* kernel_for(int dtype, int kind, int vw) {
+#define BSPL_KINDS(T)                                              \
+    switch (kind) {                                                \
+    case BSPL_V: return pick_kernel<T, BSPL_V, MAXT>(vw);          \
+    case BSPL_VGL: return pick_kernel<T, BSPL_VGL, MAXT>(vw);      \
+    case BSPL_VGH: return pick_kernel<T, BSPL_VGH, MAXT>(vw);      \
+    }                                                              \
+    return nullptr;
+    switch (dtype) {
+    case BSPL_F32: { BSPL_KINDS(F32) }
+    case BSPL_F16: { BSPL_KINDS(F16) }
+    case BSPL_BF16: { BSPL_KINDS(BF16) }
+    }
+#undef BSPL_KINDS
+    return nullptr;
+}
+
+template <int MAXT>
+bspl_status launch(const void* fn, const KernelArgs<MAXT>& a, const bspl_tile& tile,
+                   hipStream_t s) {
+    if (!fn) return fail(BSPL_EINVAL, "no kernel for this dtype/kind/vw");
+    if (a.total_groups <= 0) return BSPL_OK;
+    int64_t grid = a.total_groups;
+    if (tile.grid > 0 && tile.grid < grid) grid = tile.grid;
+    dim3 block(64 * tile.wx * tile.wy);
+    void* args[] = {const_cast<KernelArgs<MAXT>*>(&a)};
+    BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), block, args, 0, s));
+    return BSPL_OK;
+}
+
+}  // namespace
+
+bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
+                          const bspl_tile& tile, hipStream_t s) {
+    KernelArgs<1> a;
+    a.t[0] = d;
+    a.t[0].groups_begin = 0;
+    a.ntables = 1;
+    a.wx = tile.wx;
+    a.wy = tile.wy;
+    const int64_t ygroups = (d.npos + tile.wy - 1) / tile.wy;
+    a.total_groups = ygroups * d.xgroups;
+    return launch<1>(kernel_for<1>(t->info.dtype, kind, tile.vw), a, tile, s);
+}
+
+bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
+                         const bspl_tile& tile, hipStream_t s) {
+    return launch<kMaxTables>(kernel_for<kMaxTables>(dtype, kind, tile.vw), a, tile, s);
+}
+
+const void* multi_kernel_ptr(int dtype, int kind, int vw) {
+    return kernel_for<kMaxTables>(dtype, kind, vw);
+}
+
+}  // namespace bspl

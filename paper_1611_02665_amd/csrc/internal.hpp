@@ -1,0 +1,105 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "bspline.h"
+
+struct bspl_table {
+    bspl_table_info info;   // data / scales point at d_table / d_scales
+    void* d_table = nullptr;
+    float* d_scales = nullptr;
+    int device = 0;
+};
+
+namespace bspl {
+
+// Most tables one batched launch can hold.
+constexpr int kMaxTables = 16;
+
+// Record a failure message for spline_last_error() and return the status.
+bspl_status fail(bspl_status s, const char* fmt, ...);
+bspl_status hip_fail(hipError_t e, const char* what);
+
+#define BSPL_HIP(call)                                        \
+    do {                                                      \
+        hipError_t bspl_e_ = (call);                          \
+        if (bspl_e_ != hipSuccess)                            \
+            return ::bspl::hip_fail(bspl_e_, #call);          \
+    } while (0)
+
+// Everything a kernel needs to evaluate one table for one set of positions.
+// Byte strides are 32-bit: the whole 4x4x4 row block of a cell lies within
+// 4 GiB of its first row (checked at table creation).
+struct TableDesc {
+    const char* table;        // padded table
+    const float* scales;      // per-spline scales (F16/BF16) or nullptr
+    const double* pos;        // [3][npos]
+    float* v;
+    float* g;
+    float* lh;
+    int64_t npos;
+    int64_t ldo;
+    int64_t groups_begin;     // first workgroup-block index of this table
+    double inv_delta[3];      // n_d / L_d
+    float inv_delta_f[3];
+    int32_t ncell[3];
+    uint32_t row_bytes;       // bytes between consecutive z rows
+    uint32_t ystride;         // bytes between consecutive y planes
+    uint32_t xstride;         // bytes between consecutive x planes
+    int32_t nsplines;
+    int32_t nchunks;          // spline tiles of 64*vw covering nsplines
+    int32_t xgroups;          // blocks along splines: ceil(nchunks / wx)
+    int32_t vec_store;        // outputs allow vw-wide vector stores
+};
+
+template <int MAXT>
+struct KernelArgs {
+    TableDesc t[MAXT];
+    int64_t total_groups;
+    int32_t ntables;
+    int32_t wx;
+    int32_t wy;
+};
+
+// Fill a descriptor for table t (positions and outputs included).
+bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, float* v,
+                      float* g, float* lh, int64_t ldo, int vw, int wx, int wy,
+                      TableDesc* out);
+
+bool tile_valid(const bspl_tile& tile, int dtype);
+bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos);
+
+// Kernel launchers (eval_kernels.hip).
+bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
+                          const bspl_tile& tile, hipStream_t s);
+bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
+                         const bspl_tile& tile, hipStream_t s);
+// Address of the batched kernel for a configuration (graph node building).
+const void* multi_kernel_ptr(int dtype, int kind, int vw);
+
+// Table layout kernels (layout_kernels.hip).
+bspl_status build_table(bspl_table* t, const float* d_coefs, bool padded_input,
+                        hipStream_t s);
+
+// Wisdom cache (autotune.cpp).
+bool wisdom_lookup(const char* key, bspl_tile* out);
+void wisdom_store(const char* key, const bspl_tile& tile);
+void wisdom_key(char* buf, size_t n, int dtype, int kind, int64_t nsplines,
+                const int32_t ncell[3], int64_t npos, const char* prefix);
+
+int device_cu_count();
+
+// Autotuner pieces shared with the batched planner (autotune.cpp).
+std::vector<bspl_tile> tile_candidates(int dtype, int64_t max_nsplines, bool persistent);
+bspl_status fill_random_positions(double* pos, int64_t npos, const double box[3], uint64_t salt,
+                                  hipStream_t s);
+bspl_status sweep(const std::vector<bspl_tile>& cands, hipStream_t s,
+                  bspl_status (*run)(void*, const bspl_tile&, int), void* ctx, bspl_tile* best,
+                  float* best_us);
+bspl_status record_wisdom(const char* path, const char* key, const bspl_tile& t, float us);
+
+}  // namespace bspl

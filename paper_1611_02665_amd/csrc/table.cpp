@@ -1,0 +1,292 @@
+// Host side of the C ABI: status reporting, table layout and lifetime, and
+// the single-table evaluation entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace bspl {
+
+namespace {
+thread_local char g_last_error[512] = "";
+}
+
+bspl_status fail(bspl_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+bspl_status hip_fail(hipError_t e, const char* what) {
+    const bspl_status s = (e == hipErrorOutOfMemory) ? BSPL_ENOMEM : BSPL_EDEVICE;
+    return fail(s, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+int device_cu_count() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+        return 256;
+    return n;
+}
+
+bool tile_valid(const bspl_tile& tile, int dtype) {
+    const bool f32 = dtype == BSPL_F32;
+    const bool vw_ok = f32 ? (tile.vw == 1 || tile.vw == 2 || tile.vw == 4)
+                           : (tile.vw == 2 || tile.vw == 4 || tile.vw == 8);
+    return vw_ok && tile.wx >= 1 && tile.wy >= 1 && tile.wx * tile.wy <= 8 && tile.grid >= 0;
+}
+
+bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos) {
+    (void)kind;
+    (void)npos;
+    const int64_t n = t->info.n_splines;
+    bspl_tile tile{};
+    if (t->info.dtype == BSPL_F32)
+        tile.vw = n >= 256 ? 4 : (n >= 128 ? 2 : 1);
+    else
+        tile.vw = n >= 512 ? 8 : (n >= 256 ? 4 : 2);
+    const int64_t chunks = (n + 64 * tile.vw - 1) / (64 * tile.vw);
+    tile.wx = (int)std::min<int64_t>(4, chunks);
+    tile.wy = std::max(1, 4 / tile.wx);
+    tile.grid = 0;
+    return tile;
+}
+
+static bool aligned(const void* p, int bytes) {
+    return p == nullptr || (reinterpret_cast<uintptr_t>(p) % (uintptr_t)bytes) == 0;
+}
+
+bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, float* v, float* g,
+                      float* lh, int64_t ldo, int vw, int wx, int wy, TableDesc* out) {
+    const bspl_table_info& in = t->info;
+    TableDesc d{};
+    d.table = static_cast<const char*>(t->d_table);
+    d.scales = t->d_scales;
+    d.pos = pos;
+    d.v = v;
+    d.g = g;
+    d.lh = lh;
+    d.npos = npos;
+    d.ldo = ldo;
+    d.groups_begin = 0;
+    const int ncell[3] = {in.nx, in.ny, in.nz};
+    for (int k = 0; k < 3; ++k) {
+        d.ncell[k] = ncell[k];
+        d.inv_delta[k] = (double)ncell[k] / in.box[k];
+        d.inv_delta_f[k] = (float)d.inv_delta[k];
+    }
+    d.row_bytes = (uint32_t)in.row_bytes;
+    d.ystride = (uint32_t)((int64_t)in.pz * in.row_bytes);
+    d.xstride = (uint32_t)((int64_t)in.py * in.pz * in.row_bytes);
+    d.nsplines = (int32_t)in.n_splines;
+    d.nchunks = (int32_t)((in.n_splines + 64 * vw - 1) / (64 * vw));
+    d.xgroups = (d.nchunks + wx - 1) / wx;
+    const int vb = 4 * vw;
+    d.vec_store = (ldo % vw == 0) && aligned(v, vb) && aligned(g, vb) && aligned(lh, vb) ? 1 : 0;
+    const int64_t groups = (int64_t)d.xgroups * ((npos + wy - 1) / wy);
+    if (groups > INT32_MAX)
+        return fail(BSPL_EUNSUPPORTED, "too many work blocks (%lld)", (long long)groups);
+    *out = d;
+    return BSPL_OK;
+}
+
+}  // namespace bspl
+
+using namespace bspl;
+
+extern "C" {
+
+const char* spline_status_string(bspl_status s) {
+    switch (s) {
+    case BSPL_OK: return "BSPL_OK";
+    case BSPL_EINVAL: return "BSPL_EINVAL: invalid argument";
+    case BSPL_ENOMEM: return "BSPL_ENOMEM: out of memory";
+    case BSPL_EDEVICE: return "BSPL_EDEVICE: HIP runtime error";
+    case BSPL_EUNSUPPORTED: return "BSPL_EUNSUPPORTED: unsupported request";
+    case BSPL_EIO: return "BSPL_EIO: wisdom file error";
+    }
+    return "unknown bspl_status";
+}
+
+const char* spline_last_error(void) { return g_last_error; }
+
+bspl_status spline_layout_query(int nx, int ny, int nz, int64_t n_splines, bspl_dtype dtype,
+                                bspl_table_info* out) {
+    if (!out) return fail(BSPL_EINVAL, "out is NULL");
+    if (nx <= 0 || ny <= 0 || nz <= 0 || n_splines <= 0)
+        return fail(BSPL_EINVAL, "grid (%d,%d,%d) and n_splines %lld must be positive", nx, ny,
+                    nz, (long long)n_splines);
+    if (dtype != BSPL_F32 && dtype != BSPL_F16 && dtype != BSPL_BF16)
+        return fail(BSPL_EINVAL, "bad dtype %d", (int)dtype);
+    if (n_splines > (int64_t)1 << 30 || nx > (1 << 28) || ny > (1 << 28) || nz > (1 << 28))
+        return fail(BSPL_EUNSUPPORTED, "sizes beyond 2^30 splines or 2^28 cells");
+    bspl_table_info i{};
+    i.nx = nx; i.ny = ny; i.nz = nz;
+    i.px = nx + 3; i.py = ny + 3; i.pz = nz + 3;
+    i.n_splines = n_splines;
+    i.dtype = dtype;
+    i.elem_bytes = dtype == BSPL_F32 ? 4 : 2;
+    const int64_t per_row = 128 / i.elem_bytes;
+    i.n_padded = (n_splines + per_row - 1) / per_row * per_row;
+    i.row_bytes = i.n_padded * i.elem_bytes;
+    // overflow-checked px*py*pz*row_bytes
+    const double est = (double)i.px * i.py * i.pz * (double)i.row_bytes;
+    if (est > 9.0e18) return fail(BSPL_EUNSUPPORTED, "table of %.3g bytes overflows", est);
+    i.table_bytes = (int64_t)i.px * i.py * i.pz * i.row_bytes;
+    // the 4x4x4 block of a cell must span < 4 GiB (32-bit offsets in kernels)
+    const double span = 3.0 * ((double)i.py * i.pz * i.row_bytes + (double)i.pz * i.row_bytes +
+                               (double)i.row_bytes) + (double)i.row_bytes;
+    if (span >= 4294967296.0)
+        return fail(BSPL_EUNSUPPORTED, "one cell's row block spans %.3g bytes (>= 4 GiB)", span);
+    i.box[0] = i.box[1] = i.box[2] = 1.0;
+    *out = i;
+    return BSPL_OK;
+}
+
+bspl_status spline_table_create(bspl_table** out, int nx, int ny, int nz, int64_t n_splines,
+                                const float* coefs, bspl_dtype dtype, const double box[3],
+                                unsigned flags, void* stream) {
+    if (!out) return fail(BSPL_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!coefs) return fail(BSPL_EINVAL, "coefs is NULL");
+    if (flags & ~(BSPL_COEFS_PADDED | BSPL_COEFS_DEVICE))
+        return fail(BSPL_EINVAL, "unknown flags 0x%x", flags);
+    bspl_table_info info{};
+    bspl_status st = spline_layout_query(nx, ny, nz, n_splines, dtype, &info);
+    if (st != BSPL_OK) return st;
+    if (box) {
+        for (int k = 0; k < 3; ++k) {
+            if (!(box[k] > 0.0) || !std::isfinite(box[k]))
+                return fail(BSPL_EINVAL, "box[%d] = %g must be finite and > 0", k, box[k]);
+            info.box[k] = box[k];
+        }
+    }
+    const bool padded = (flags & BSPL_COEFS_PADDED) != 0;
+    const int64_t src_elems = padded ? (int64_t)info.px * info.py * info.pz * n_splines
+                                     : (int64_t)nx * ny * nz * n_splines;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    bspl_table* t = new (std::nothrow) bspl_table();
+    if (!t) return fail(BSPL_ENOMEM, "host allocation");
+    t->info = info;
+    (void)hipGetDevice(&t->device);
+    hipError_t e = hipMalloc(&t->d_table, (size_t)info.table_bytes);
+    if (e != hipSuccess) {
+        delete t;
+        return hip_fail(e, "hipMalloc(table)");
+    }
+    if (dtype != BSPL_F32) {
+        e = hipMalloc((void**)&t->d_scales, sizeof(float) * (size_t)info.n_padded);
+        if (e != hipSuccess) {
+            (void)hipFree(t->d_table);
+            delete t;
+            return hip_fail(e, "hipMalloc(scales)");
+        }
+    }
+    const float* d_src = coefs;
+    float* staging = nullptr;
+    if (!(flags & BSPL_COEFS_DEVICE)) {
+        e = hipMalloc((void**)&staging, sizeof(float) * (size_t)src_elems);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(staging, coefs, sizeof(float) * (size_t)src_elems,
+                               hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) {
+            if (staging) (void)hipFree(staging);
+            spline_table_destroy(t);
+            return hip_fail(e, "staging coefficients on the device");
+        }
+        d_src = staging;
+    }
+    st = build_table(t, d_src, padded, s);
+    if (staging) (void)hipFree(staging);
+    if (st != BSPL_OK) {
+        spline_table_destroy(t);
+        return st;
+    }
+    t->info.data = t->d_table;
+    t->info.scales = t->d_scales;
+    *out = t;
+    return BSPL_OK;
+}
+
+bspl_status spline_table_destroy(bspl_table* t) {
+    if (!t) return BSPL_OK;
+    if (t->d_table) (void)hipFree(t->d_table);
+    if (t->d_scales) (void)hipFree(t->d_scales);
+    delete t;
+    return BSPL_OK;
+}
+
+bspl_status spline_table_info(const bspl_table* t, bspl_table_info* out) {
+    if (!t || !out) return fail(BSPL_EINVAL, "table or out is NULL");
+    *out = t->info;
+    return BSPL_OK;
+}
+
+bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos,
+                               bspl_tile* out) {
+    if (!t || !out) return fail(BSPL_EINVAL, "table or out is NULL");
+    if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
+    char key[256];
+    const int32_t nc[3] = {t->info.nx, t->info.ny, t->info.nz};
+    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos, "single");
+    bspl_tile tile;
+    if (wisdom_lookup(key, &tile) && tile_valid(tile, t->info.dtype)) {
+        *out = tile;
+        return BSPL_OK;
+    }
+    *out = default_tile(t, kind, npos);
+    return BSPL_OK;
+}
+
+bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const double* pos,
+                        float* v, float* g, float* lh, int64_t ldo, const bspl_tile* tile,
+                        void* stream) {
+    if (!t) return fail(BSPL_EINVAL, "table is NULL");
+    if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
+    if (npos < 0) return fail(BSPL_EINVAL, "npos %lld < 0", (long long)npos);
+    if (ldo < t->info.n_splines)
+        return fail(BSPL_EINVAL, "ldo %lld < n_splines %lld", (long long)ldo,
+                    (long long)t->info.n_splines);
+    if (npos == 0) return BSPL_OK;
+    if (npos > INT32_MAX) return fail(BSPL_EUNSUPPORTED, "npos beyond 2^31-1");
+    if (!pos || !v) return fail(BSPL_EINVAL, "pos or v is NULL");
+    if (kind != BSPL_V && (!g || !lh)) return fail(BSPL_EINVAL, "g or l/h is NULL");
+    bspl_tile tl;
+    if (tile) {
+        tl = *tile;
+        if (!tile_valid(tl, t->info.dtype))
+            return fail(BSPL_EINVAL, "tile (vw=%d wx=%d wy=%d grid=%d) invalid for dtype %d",
+                        tl.vw, tl.wx, tl.wy, tl.grid, t->info.dtype);
+    } else {
+        spline_tile_select(t, kind, npos, &tl);
+    }
+    TableDesc d;
+    bspl_status st = make_desc(t, npos, pos, v, kind == BSPL_V ? nullptr : g,
+                               kind == BSPL_V ? nullptr : lh, ldo, tl.vw, tl.wx, tl.wy, &d);
+    if (st != BSPL_OK) return st;
+    return launch_single(t, kind, d, tl, static_cast<hipStream_t>(stream));
+}
+
+bspl_status spline_eval_v(const bspl_table* t, int64_t npos, const double* pos, float* v,
+                          int64_t ldo, void* stream) {
+    return spline_eval(t, BSPL_V, npos, pos, v, nullptr, nullptr, ldo, nullptr, stream);
+}
+
+bspl_status spline_eval_vgl(const bspl_table* t, int64_t npos, const double* pos, float* v,
+                            float* g, float* l, int64_t ldo, void* stream) {
+    return spline_eval(t, BSPL_VGL, npos, pos, v, g, l, ldo, nullptr, stream);
+}
+
+bspl_status spline_eval_vgh(const bspl_table* t, int64_t npos, const double* pos, float* v,
+                            float* g, float* h, int64_t ldo, void* stream) {
+    return spline_eval(t, BSPL_VGH, npos, pos, v, g, h, ldo, nullptr, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+"""C ABI checks that need no GPU: exported symbols, layout arithmetic,
+status codes and argument validation (which happens before any HIP call)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1611_02665_amd import binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "bspline.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(spline_\w+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported_and_bound():
+    names = _declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(B.lib, n), f"{n} missing from libbspline.so"
+        assert n in B.EXPORTED, f"{n} has no binding"
+    assert sorted(B.EXPORTED) == names
+
+
+def test_status_strings():
+    for s in range(6):
+        assert B.spline_status_string(s).startswith("BSPL_")
+    assert "unknown" in B.spline_status_string(99)
+
+
+@pytest.mark.parametrize("shape,dtype,np_,nbytes", [
+    ((16, 16, 16, 64), "f32", 64, 19**3 * 64 * 4),
+    ((48, 48, 48, 2048), "f32", 2048, 1_086_676_992),
+    ((48, 48, 48, 2048), "f16", 2048, 543_338_496),
+    ((48, 48, 48, 2048), "bf16", 2048, 543_338_496),
+    ((96, 96, 96, 4096), "f32", 4096, 15_897_378_816),
+    ((96, 96, 96, 4096), "f16", 4096, 7_948_689_408),
+    ((64, 64, 64, 2048), "f32", 2048, 67**3 * 2048 * 4),
+    ((3, 4, 5, 33), "f32", 64, 6 * 7 * 8 * 64 * 4),
+    ((3, 4, 5, 33), "f16", 64, 6 * 7 * 8 * 64 * 2),
+    ((48, 48, 60, 128), "f32", 128, 51 * 51 * 63 * 128 * 4),
+])
+def test_layout_query(shape, dtype, np_, nbytes):
+    info = B.spline_layout_query(*shape, dtype)
+    assert info["n_padded"] == np_
+    assert info["row_bytes"] % 128 == 0
+    assert (info["px"], info["py"], info["pz"]) == tuple(s + 3 for s in shape[:3])
+    assert info["table_bytes"] == nbytes
+    assert info["data"] is None and info["scales"] is None
+
+
+def test_layout_query_rejects():
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_layout_query(0, 4, 4, 8)
+    assert e.value.status == B.BSPL_EINVAL
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_layout_query(4, 4, 4, 8, 7)
+    assert e.value.status == B.BSPL_EINVAL
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_layout_query(4, 4, 4, -1)
+    assert e.value.status == B.BSPL_EINVAL
+    # a single cell's 4x4x4 row block would span more than 4 GiB
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_layout_query(4096, 4096, 4096, 4096)
+    assert e.value.status == B.BSPL_EUNSUPPORTED
+
+
+def test_create_validates_before_touching_the_device():
+    h = ctypes.c_void_p(1234)
+    coefs = (ctypes.c_float * 8)()
+    assert B.lib.spline_table_create(None, 1, 1, 1, 8, coefs, 0, None, 0, None) == B.BSPL_EINVAL
+    assert B.lib.spline_table_create(ctypes.byref(h), 1, 1, 1, 8, None, 0, None, 0, None) \
+        == B.BSPL_EINVAL
+    assert h.value is None  # *out is cleared on failure
+    assert B.lib.spline_table_create(ctypes.byref(h), 0, 1, 1, 8, coefs, 0, None, 0, None) \
+        == B.BSPL_EINVAL
+    assert B.lib.spline_table_create(ctypes.byref(h), 1, 1, 1, 8, coefs, 5, None, 0, None) \
+        == B.BSPL_EINVAL
+    assert B.lib.spline_table_create(ctypes.byref(h), 1, 1, 1, 8, coefs, 0, None, 0x80, None) \
+        == B.BSPL_EINVAL
+    bad_box = (ctypes.c_double * 3)(1.0, -1.0, 1.0)
+    assert B.lib.spline_table_create(ctypes.byref(h), 1, 1, 1, 8, coefs, 0, bad_box, 0, None) \
+        == B.BSPL_EINVAL
+    assert "box" in B.spline_last_error()
+    nan_box = (ctypes.c_double * 3)(1.0, float("nan"), 1.0)
+    assert B.lib.spline_table_create(ctypes.byref(h), 1, 1, 1, 8, coefs, 0, nan_box, 0, None) \
+        == B.BSPL_EINVAL
+
+
+def test_null_handles():
+    assert B.lib.spline_table_destroy(None) == B.BSPL_OK
+    assert B.lib.spline_batch_plan_destroy(None) == B.BSPL_OK
+    info = B.bspl_table_info()
+    assert B.lib.spline_table_info(None, ctypes.byref(info)) == B.BSPL_EINVAL
+    for fn in ("spline_eval_v",):
+        assert getattr(B.lib, fn)(None, 1, None, None, 1, None) == B.BSPL_EINVAL
+    assert B.lib.spline_eval_vgh(None, 1, None, None, None, None, 1, None) == B.BSPL_EINVAL
+    assert B.lib.spline_eval_vgl(None, 1, None, None, None, None, 1, None) == B.BSPL_EINVAL
+    assert B.lib.spline_eval(None, 2, 1, None, None, None, None, 1, None, None) == B.BSPL_EINVAL
+    t = B.bspl_tile()
+    assert B.lib.spline_tile_select(None, 0, 1, ctypes.byref(t)) == B.BSPL_EINVAL
+    assert B.lib.spline_autotune(None, 0, 1, None, None, None) == B.BSPL_EINVAL
+    assert B.lib.spline_batch_execute(None, None) == B.BSPL_EINVAL
+    assert B.lib.spline_batch_rebind(None, 0, None, None, None, None) == B.BSPL_EINVAL
+    assert B.lib.spline_batch_plan_tile(None, ctypes.byref(t)) == B.BSPL_EINVAL
+
+
+def test_batch_plan_argument_checks():
+    h = ctypes.c_void_p()
+    z64 = (ctypes.c_int64 * 17)()
+    zp = (ctypes.c_void_p * 17)()
+    args = (zp, z64, 2, zp, zp, zp, zp, z64, None, None, None)
+    assert B.lib.spline_batch_plan_create(ctypes.byref(h), 0, *args) == B.BSPL_EINVAL
+    assert B.lib.spline_batch_plan_create(ctypes.byref(h), 17, *args) == B.BSPL_EINVAL
+    assert B.lib.spline_batch_plan_create(None, 1, *args) == B.BSPL_EINVAL
+    # NULL table pointer inside the array
+    assert B.lib.spline_batch_plan_create(ctypes.byref(h), 1, *args) == B.BSPL_EINVAL
+    assert "table 0" in B.spline_last_error()
+
+
+def test_wisdom_files(tmp_path):
+    missing = str(tmp_path / "missing.txt")
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_wisdom_load(missing)
+    assert e.value.status == B.BSPL_EIO
+    p = tmp_path / "w.txt"
+    p.write_text("# comment\nsingle|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 12.5\n"
+                 "garbage line\n")
+    B.spline_wisdom_load(str(p))
+    out = str(tmp_path / "out.txt")
+    B.spline_wisdom_save(out)
+    text = open(out).read()
+    assert "single|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0" in text
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_wisdom_save(str(tmp_path / "no" / "such" / "dir.txt"))
+    assert e.value.status == B.BSPL_EIO

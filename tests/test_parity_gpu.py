@@ -1,0 +1,338 @@
+"""GPU parity: the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerance (FP32 tables): per output component, max |gpu - oracle| divided by
+max |oracle| over all positions and splines must be <= 1e-5.  FP16/BF16
+tables are checked against the oracle run on the dequantised coefficients to
+the same 1e-5 (this isolates the kernel), and against the original
+coefficients to a stated bound (2e-3 FP16, 5e-3 BF16).
+"""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import (FP32_TOL, assert_canary, assert_close, bf16_to_f32, dequantized,
+                     normalized_errors, padded_layout, quantize_bf16, quantize_f16, run_gpu)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1611_02665_amd import binding as B  # noqa: E402
+
+
+class Table:
+    def __init__(self, coef, dtype="f32", box=None, flags=0):
+        nx, ny, nz, n = coef.shape
+        if flags & B.BSPL_COEFS_PADDED:
+            nx, ny, nz = nx - 3, ny - 3, nz - 3
+        self.n = n
+        self.h = B.spline_table_create(nx, ny, nz, n, np.ascontiguousarray(coef, np.float32),
+                                       dtype, box, flags)
+
+    def close(self):
+        if self.h:
+            B.spline_table_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+# ---------------------------------------------------------------- config 1
+@pytest.fixture(scope="module")
+def cfg1():
+    coef = synth.coef_table(16, 16, 16, 64, stream=synth.table_stream(0))
+    pos = synth.positions(1024, stream=synth.position_stream(0))
+    with Table(coef) as t:
+        yield coef, pos, t
+
+
+@pytest.mark.parametrize("kind", ["v", "vgl", "vgh"])
+def test_config1_plain_fp32(cfg1, kind):
+    coef, pos, t = cfg1
+    gpu, raw = run_gpu(B, t.h, kind, pos, 64, ldo=72)
+    assert_canary(raw, 64)
+    ref = oracle.evaluate(kind, coef, pos)
+    errs = assert_close(kind, gpu, ref, label=f"config1 {kind}")
+    print(kind, {k: f"{e:.2e}" for k, e in errs.items()})
+
+
+def test_cross_kind_consistency(cfg1):
+    coef, pos, t = cfg1
+    v, _ = run_gpu(B, t.h, "v", pos, 64)
+    l, _ = run_gpu(B, t.h, "vgl", pos, 64)
+    h, _ = run_gpu(B, t.h, "vgh", pos, 64)
+    vs = np.abs(h["v"]).max()
+    assert np.abs(v["v"] - h["v"]).max() <= 1e-6 * vs
+    assert np.abs(l["v"] - h["v"]).max() <= 1e-6 * vs
+    gs = np.abs(h["g"]).max()
+    assert np.abs(l["g"] - h["g"]).max() <= 1e-6 * gs
+    tr = h["h"][:, 0] + h["h"][:, 3] + h["h"][:, 5]
+    assert np.abs(l["l"] - tr).max() <= 1e-5 * np.abs(tr).max()
+
+
+# ------------------------------------------------------- every tile shape
+def _tiles(dtype):
+    vws = (1, 2, 4) if dtype == "f32" else (2, 4, 8)
+    shapes = [(1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (1, 4), (2, 2), (4, 2), (2, 4), (1, 8)]
+    for vw, (wx, wy), grid in itertools.product(vws, shapes, (0, 7)):
+        yield (vw, wx, wy, grid)
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # 7x9x5 grid, N = 300 (ragged last spline tile for every vw), box not
+    # the unit cube, 37 positions including negative and far images
+    coef = synth.coef_table(7, 9, 5, 300, stream=11)
+    box = (1.3, 0.8, 2.1)
+    pos = synth.positions(37, stream=12) * 6.0 - 2.5
+    pos *= np.array(box)[:, None]
+    return coef, box, pos
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_all_tiles_ragged(ragged, dtype):
+    coef, box, pos = ragged
+    deq = dequantized(coef, dtype)
+    refs = {k: oracle.evaluate(k, deq, pos, box=box) for k in ("v", "vgl", "vgh")}
+    with Table(coef, dtype, box) as t:
+        for tile in _tiles(dtype):
+            for kind in ("v", "vgl", "vgh"):
+                gpu, raw = run_gpu(B, t.h, kind, pos, 300, ldo=301, tile=tile)
+                assert_canary(raw, 300)
+                assert_close(kind, gpu, refs[kind], label=f"{dtype} tile {tile} {kind}")
+
+
+def test_invalid_tiles_rejected(cfg1):
+    _, pos, t = cfg1
+    for tile in [(3, 1, 1, 0), (8, 1, 1, 0), (4, 0, 1, 0), (4, 4, 4, 0), (4, 1, 1, -1)]:
+        with pytest.raises(B.BsplineError) as e:
+            run_gpu(B, t.h, "vgh", pos[:, :4], 64, tile=tile)
+        assert e.value.status == B.BSPL_EINVAL
+
+
+# ------------------------------------------------------------ edge cases
+def test_edge_positions(cfg1):
+    coef, pos, t = cfg1
+    base = pos[:, :64]
+    ref = oracle.evaluate("vgh", coef, base)
+    for k, tol in ((np.array([1, -2, 3]), FP32_TOL), (np.array([-40, 17, 9]), FP32_TOL),
+                   (np.array([10**6, -10**6, 10**6]), 1e-4)):
+        gpu, _ = run_gpu(B, t.h, "vgh", base + k[:, None].astype(np.float64), 64)
+        assert_close("vgh", gpu, ref, tol=tol, label=f"image {k}")
+    # tiny negatives and exact faces: compare with the oracle on the same input
+    odd = np.array([[-1e-300, 0.0, 1.0, 0.5, np.nextafter(1.0, 0), -0.0625],
+                    [-1e-17, 1.0, 0.0, 0.25, 0.125, 3.0],
+                    [0.0, -1.0, 2.0, np.nextafter(0.0, 1), 0.75, -7.0]])
+    gpu, _ = run_gpu(B, t.h, "vgh", odd, 64)
+    assert_close("vgh", gpu, oracle.evaluate("vgh", coef, odd), label="odd positions")
+
+
+def test_non_finite_and_far_positions(cfg1):
+    _, _, t = cfg1
+    pos = np.array([[0.1, np.nan, 0.3, np.inf, 1e300, -1e300, 0.2],
+                    [0.2, 0.2, -np.inf, 0.1, 0.5, 0.5, 1e17],
+                    [0.3, 0.3, 0.3, 0.1, 0.5, 0.5, 0.5]])
+    for kind in ("v", "vgl", "vgh"):
+        gpu, _ = run_gpu(B, t.h, kind, pos, 64)
+        for key, a in gpu.items():
+            assert np.all(np.isfinite(a[0])), (kind, key)
+            assert np.all(np.isnan(a[1])) and np.all(np.isnan(a[2])) and np.all(np.isnan(a[3]))
+            # no fraction bits left: evaluated at some grid point, finite
+            assert np.all(np.isfinite(a[4:])), (kind, key)
+
+
+def test_empty_batch_and_argument_errors(cfg1):
+    _, pos, t = cfg1
+    v = torch.empty(1, 64, device="cuda")
+    B.spline_eval_v(t.h, 0, None, None, 64)  # npos = 0 is a no-op
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_eval_v(t.h, 4, None, v, 64)
+    assert e.value.status == B.BSPL_EINVAL
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_eval_v(t.h, 1, torch.zeros(3, 1, dtype=torch.float64, device="cuda"), v, 63)
+    assert e.value.status == B.BSPL_EINVAL
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1), (1, 2, 3, 5), (2, 2, 2, 33), (48, 48, 60, 128),
+                                   (5, 4, 3, 1000)])
+def test_shapes(shape):
+    coef = synth.coef_table(*shape, stream=21)
+    box = (1.0, 1.1, 0.9)
+    pos = (synth.positions(50, stream=22) * 3 - 1) * np.array(box)[:, None]
+    with Table(coef, box=box) as t:
+        for kind in ("v", "vgl", "vgh"):
+            gpu, _ = run_gpu(B, t.h, kind, pos, shape[3])
+            assert_close(kind, gpu, oracle.evaluate(kind, coef, pos, box=box),
+                         label=f"{shape} {kind}")
+
+
+def test_unaligned_ldo_and_outputs(cfg1):
+    coef, pos, t = cfg1
+    p = pos[:, :40]
+    ref = oracle.evaluate("vgh", coef, p)
+    # ldo not a multiple of the lane width: scalar stores
+    gpu, raw = run_gpu(B, t.h, "vgh", p, 64, ldo=67)
+    assert_canary(raw, 64)
+    assert_close("vgh", gpu, ref, label="ldo 67")
+    # output pointers offset by one float (not 16-byte aligned)
+    dev = torch.device("cuda")
+    pd = torch.from_numpy(p).to(dev)
+    big = torch.full((1 + 40 * 64 * 10,), 7.0, device=dev)
+    v = big[1:1 + 40 * 64]
+    g = big[1 + 40 * 64:1 + 4 * 40 * 64]
+    h = big[1 + 4 * 40 * 64:]
+    B.spline_eval_vgh(t.h, 40, pd, v, g, h, 64)
+    torch.cuda.synchronize()
+    gpu = {"v": v.view(40, 64).cpu().double().numpy(),
+           "g": g.view(40, 3, 64).cpu().double().numpy(),
+           "h": h.view(40, 6, 64).cpu().double().numpy()}
+    assert_close("vgh", gpu, ref, label="misaligned outputs")
+    assert big[0].item() == 7.0
+
+
+# -------------------------------------------- polynomial reproduction (P3)
+def test_padded_polynomial_reproduction():
+    nx, ny, nz = 5, 6, 7
+    box = (1.3, 0.7, 2.1)
+
+    def f(deg, m):
+        return [np.ones_like(m), m, m * m - 1.0 / 3.0, m**3 - m][deg]
+
+    mx, my, mz = (np.arange(n + 3, dtype=np.float64) - 1 for n in (nx, ny, nz))
+    degs = [(a, b, c) for a in range(4) for b in range(4) for c in range(4)]
+    tab = np.stack([f(a, mx)[:, None, None] * f(b, my)[None, :, None] * f(c, mz)[None, None, :]
+                    for a, b, c in degs], axis=-1).astype(np.float32)
+    pos = synth.positions(100, stream=31) * np.array(box)[:, None]
+    with Table(tab, box=box, flags=B.BSPL_COEFS_PADDED) as t:
+        gpu, _ = run_gpu(B, t.h, "vgh", pos, 64)
+    d = np.array(box) / np.array([nx, ny, nz])
+    u = pos / d[:, None]
+
+    def pd(deg, x, k):
+        if k > deg:
+            return np.zeros_like(x)
+        c = np.prod([deg - i for i in range(k)]) if k else 1.0
+        return c * x ** (deg - k)
+
+    for col, (a, b, c) in enumerate(degs):
+        def comp(i, j, k):
+            return pd(a, u[0], i) * pd(b, u[1], j) * pd(c, u[2], k) / (d[0]**i * d[1]**j * d[2]**k)
+        exact = {"v": comp(0, 0, 0),
+                 "g": np.stack([comp(1, 0, 0), comp(0, 1, 0), comp(0, 0, 1)], 1),
+                 "h": np.stack([comp(2, 0, 0), comp(1, 1, 0), comp(1, 0, 1), comp(0, 2, 0),
+                                comp(0, 1, 1), comp(0, 0, 2)], 1)}
+        # the table holds FP32 roundings of the exact coefficients
+        scale_v = max(1.0, np.abs(exact["v"]).max())
+        assert np.abs(gpu["v"][:, col] - exact["v"]).max() <= 2e-5 * scale_v, (a, b, c)
+        for k in range(3):
+            e = exact["g"][:, k]
+            s = max(1.0 / d.min(), np.abs(e).max())
+            assert np.abs(gpu["g"][:, k, col] - e).max() <= 2e-5 * s, (a, b, c, k)
+        for k in range(6):
+            e = exact["h"][:, k]
+            s = max(1.0 / d.min()**2, np.abs(e).max())
+            assert np.abs(gpu["h"][:, k, col] - e).max() <= 2e-5 * s, (a, b, c, k)
+
+
+def test_constant_coefficients():
+    consts = np.array([1.0, -2.5, 0.125, 3.0], dtype=np.float32)
+    coef = np.broadcast_to(consts, (6, 5, 7, 4)).copy()
+    pos = synth.positions(64, stream=33) * 5 - 2
+    with Table(coef) as t:
+        gpu, _ = run_gpu(B, t.h, "vgh", pos, 4)
+        gl, _ = run_gpu(B, t.h, "vgl", pos, 4)
+    np.testing.assert_allclose(gpu["v"], np.broadcast_to(consts, (64, 4)), rtol=1e-6)
+    assert np.abs(gpu["g"]).max() <= 1e-5 * 7 * 3
+    assert np.abs(gpu["h"]).max() <= 1e-5 * 49 * 3
+    assert np.abs(gl["l"]).max() <= 1e-5 * 49 * 3
+
+
+# ------------------------------------------------------- layout readback
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_layout_readback_bit_exact(dtype):
+    coef = synth.coef_table(4, 5, 3, 70, stream=41)
+    coef[..., 5] = 0.0           # all-zero spline -> scale 1
+    coef[..., 6] *= 1e-3         # small spline -> small power-of-two scale
+    coef[0, 0, 0, 7] = -0.5      # max exactly a power of two
+    with Table(coef, dtype) as t:
+        info = B.spline_table_info(t.h)
+        np_ = info["n_padded"]
+        nbytes = info["table_bytes"]
+        raw = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        import ctypes
+        hip = B.lib  # hipMemcpy from the HIP runtime the library itself uses
+        rc = hip.hipMemcpy(ctypes.c_void_p(raw.data_ptr()), ctypes.c_void_p(info["data"]),
+                           ctypes.c_size_t(nbytes), 3)
+        assert rc == 0
+        got = raw.cpu().numpy()
+        if dtype == "f32":
+            want = padded_layout(coef, np_)
+            assert np.array_equal(got.view(np.float32).reshape(want.shape), want)
+            assert info["scales"] is None
+        else:
+            q, s = quantize_f16(coef) if dtype == "f16" else quantize_bf16(coef)
+            want = padded_layout(q, np_)
+            assert np.array_equal(got.view(np.uint16).reshape(want.shape), want.view(np.uint16))
+            sc = torch.empty(np_, dtype=torch.float32, device="cuda")
+            rc = hip.hipMemcpy(ctypes.c_void_p(sc.data_ptr()), ctypes.c_void_p(info["scales"]),
+                               ctypes.c_size_t(4 * np_), 3)
+            assert rc == 0
+            scv = sc.cpu().numpy()
+            assert np.array_equal(scv[:70], s)
+            assert np.all(scv[70:] == 1.0)
+            assert s[5] == 1.0 and s[7] == 0.5
+
+
+# --------------------------------------------------------- FP16 / BF16
+@pytest.fixture(scope="module")
+def paper_table():
+    coef = synth.coef_table(48, 48, 48, 2048, stream=synth.table_stream(0))
+    return coef
+
+
+@pytest.mark.parametrize("dtype,bound", [("f16", 2e-3), ("bf16", 5e-3)])
+def test_reduced_precision_paper_scale(paper_table, dtype, bound):
+    coef = paper_table
+    pos = synth.positions(256, stream=synth.position_stream(0), batch=3)
+    with Table(coef, dtype) as t:
+        gpu, _ = run_gpu(B, t.h, "vgh", pos, 2048)
+    ref_q = oracle.evaluate("vgh", dequantized(coef, dtype), pos)
+    assert_close("vgh", gpu, ref_q, label=f"{dtype} vs dequantised")
+    ref = oracle.evaluate("vgh", coef, pos)
+    errs = normalized_errors("vgh", gpu, ref)
+    print(dtype, {k: f"{e:.2e}" for k, e in errs.items()})
+    assert max(errs.values()) <= bound, errs
+
+
+@pytest.mark.parametrize("kind", ["vgh", "vgl"])
+def test_config2_paper_scale_fp32(paper_table, kind):
+    coef = paper_table
+    pos = synth.positions(512, stream=synth.position_stream(0))
+    with Table(coef) as t:
+        gpu, _ = run_gpu(B, t.h, kind, pos, 2048)
+    ref = oracle.evaluate(kind, coef, pos)
+    errs = assert_close(kind, gpu, ref, label=f"config2 {kind}")
+    print(kind, {k: f"{e:.2e}" for k, e in errs.items()})
+
+
+# ------------------------------------------------------------ streams
+def test_two_streams_share_a_table(cfg1):
+    coef, pos, t = cfg1
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    p1, p2 = pos[:, :300], pos[:, 300:700]
+    with torch.cuda.stream(s1):
+        a, _ = run_gpu(B, t.h, "vgh", p1, 64, stream=s1)
+    with torch.cuda.stream(s2):
+        b, _ = run_gpu(B, t.h, "vgh", p2, 64, stream=s2)
+    assert_close("vgh", a, oracle.evaluate("vgh", coef, p1))
+    assert_close("vgh", b, oracle.evaluate("vgh", coef, p2))
