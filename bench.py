@@ -1,0 +1,287 @@
+"""Benchmark: FP32 eval_vgh orbital-evals/s on the paper-scale table.
+
+Workload (one step = one eval_vgh call over one position batch): periodic
+48^3 grid (51^3 padded), N = 2048 splines, FP32 coefficients uniform in
+(-1, 1), 512 positions uniform in the unit cell per batch; 16 pre-generated
+batches are cycled so that repeated steps do not re-read the same rows
+from the Infinity Cache.  Inputs and outputs stay resident in HBM.
+
+Printed: one JSON line with value = VGH orbital-evals/s (npos * N / time),
+the HBM roofline of the kernel (algorithmic bytes 64*4 + 10*4 per eval),
+the FP64 oracle timed on the host cores as cpu_baseline, and extras: VGL on
+the same table, and FP16/BF16 tables against FP32 at 4096 positions with
+their error against the oracle.
+
+Modes for profiling: --profile (headline kernel only, few steps),
+--copy-probe (a plain device copy of known size, to scale HBM counters).
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "VGH orbital-evals/s + achieved HBM GB/s; FP16-table vs FP32 at stated err"
+HBM_PEAK_GBS = 8000.0
+GRID = (48, 48, 48)
+NSPL = 2048
+NPOS = 512
+NBATCH = 16
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_eval_vgh_f32_48cubed_N2048_512pos.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1611_02665_amd", "csrc", "eval_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(per_launch_alg_bytes):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    vals = {}
+    for line in open(PMC_FILE):
+        if line.startswith("#") or "=" not in line:
+            continue
+        k, v = line.split("=", 1)
+        vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed(torch, fn, steps, warmup):
+    for i in range(warmup):
+        fn(i)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(steps):
+        fn(i)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps  # ms per call
+
+
+def copy_probe(torch, nbytes=1 << 30, reps=20):
+    """Plain device-to-device copy of known size (counter calibration and the
+    measured copy bandwidth)."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = timed(torch, lambda i: dst.copy_(src), reps, 3)
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9, ms
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--profile", action="store_true", help="headline kernel only")
+    ap.add_argument("--copy-probe", action="store_true", help="only a 1 GiB device copy")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the evaluation "
+              "shards by replicating the table and splitting positions, with no "
+              "communication, so the per-GPU figure is the whole story.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1611_02665_amd import accounting as A
+    from paper_1611_02665_amd import binding as B
+
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        gbs, ms = copy_probe(torch)
+        print(json.dumps({"copy_probe_bytes": 1 << 30, "copy_ms": ms, "copy_gbs": gbs}))
+        return 0
+
+    t0 = time.time()
+    coef = synth.coef_table(*GRID, NSPL, stream=synth.table_stream(0))
+    log(f"[bench] coefficients generated in {time.time() - t0:.1f}s")
+    t32 = B.spline_table_create(*GRID, NSPL, coef, "f32")
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    batches = [torch.from_numpy(synth.positions(NPOS, stream=synth.position_stream(0), batch=b))
+               .to(dev) for b in range(NBATCH)]
+    ldo = NSPL
+    v = torch.empty(NPOS, ldo, device=dev)
+    g = torch.empty(NPOS, 3, ldo, device=dev)
+    h = torch.empty(NPOS, 6, ldo, device=dev)
+    l = torch.empty(NPOS, ldo, device=dev)
+    pp = [b.data_ptr() for b in batches]
+    vp, gp, hp, lp = v.data_ptr(), g.data_ptr(), h.data_ptr(), l.data_ptr()
+    tile = B.spline_tile_select(t32, "vgh", NPOS)
+    log(f"[bench] table ready, tile {tile}")
+
+    def vgh_step(i):
+        B.spline_eval_vgh(t32, NPOS, pp[i % NBATCH], vp, gp, hp, ldo, stream)
+
+    steps = 20 if args.profile else args.steps
+    warmup = 5 if args.profile else args.warmup
+    ms = timed(torch, vgh_step, steps, warmup)
+    evals = NPOS * NSPL
+    value = evals / (ms * 1e-3)
+    alg_bytes = A.batch_bytes("vgh", "f32", NPOS, NSPL)
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    log(f"[bench] VGH {ms * 1e3:.2f} us/launch, {value:.4g} evals/s, {achieved:.0f} GB/s")
+    if args.profile:
+        B.spline_table_destroy(t32)
+        return 0
+
+    traffic = read_traffic(alg_bytes)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "orbital-evals/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "eval_vgh, 48^3 periodic grid (51^3 padded) x N=2048 FP32 table "
+                        "(1.09 GB), 512 uniform positions per batch, 16 batches cycled",
+            "grid": list(GRID), "n_splines": NSPL, "npos": NPOS, "kernel": "eval_vgh",
+            "table_dtype": "f32", "tile": list(tile.as_tuple()),
+        },
+        "hbm_gbs": achieved,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+            "bytes_per_eval": A.bytes_per_eval("vgh", "f32"),
+        },
+    }
+
+    extra = {}
+    if not args.no_extras:
+        # VGL on the same table and batches
+        def vgl_step(i):
+            B.spline_eval_vgl(t32, NPOS, pp[i % NBATCH], vp, gp, lp, ldo, stream)
+        ms_l = timed(torch, vgl_step, max(100, steps // 2), warmup)
+        extra["vgl"] = {"evals_per_s": evals / (ms_l * 1e-3), "us_per_launch": ms_l * 1e3,
+                        "hbm_gbs": A.batch_bytes("vgl", "f32", NPOS, NSPL) / (ms_l * 1e-3) / 1e9}
+        copy_gbs, _ = copy_probe(torch)
+        extra["copy_gbs_measured"] = copy_gbs
+        line["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
+        extra["precision"] = precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup)
+        line["extra"] = extra
+
+    B.spline_table_destroy(t32)
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(np, synth, coef)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
+    """FP16 and BF16 tables vs FP32 on the same 4096-position batches."""
+    import oracle  # error check of the reduced-precision tables (test use of the oracle)
+    npos = 4096
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    nb = 4
+    batches = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0),
+                                                batch=100 + b)).to(dev) for b in range(nb)]
+    pp = [b.data_ptr() for b in batches]
+    v = torch.empty(npos, NSPL, device=dev)
+    g = torch.empty(npos, 3, NSPL, device=dev)
+    h = torch.empty(npos, 6, NSPL, device=dev)
+    out = {}
+    sample = synth.positions(64, stream=synth.position_stream(0), batch=100)
+    ref = oracle.evaluate("vgh", coef, sample)
+    sample_d = torch.from_numpy(sample).to(dev)  # [3][64]: npos is also the row stride
+    k = max(50, steps // 8)
+    for dt in ("f32", "f16", "bf16"):
+        t = t32 if dt == "f32" else B.spline_table_create(*GRID, NSPL, coef, dt)
+        ms = timed(torch, lambda i: B.spline_eval_vgh(t, npos, pp[i % nb], v.data_ptr(),
+                                                      g.data_ptr(), h.data_ptr(), NSPL, stream),
+                   k, warmup)
+        # error on the first 64 positions of batch 0 vs the FP64 oracle
+        B.spline_eval_vgh(t, 64, sample_d.data_ptr(), v.data_ptr(), g.data_ptr(), h.data_ptr(),
+                          NSPL, stream)
+        torch.cuda.synchronize()
+        errs = {}
+        for name, arr, refa in (("v", v[:64], ref["v"]), ("g", g[:64], ref["g"]),
+                                ("h", h[:64], ref["h"])):
+            a = arr.cpu().numpy().astype(np.float64)
+            if refa.ndim == 2:
+                errs[name] = float(np.abs(a - refa).max() / np.abs(refa).max())
+            else:
+                for c in range(refa.shape[1]):
+                    key = name + ("xyz"[c] if name == "g" else
+                                  ["xx", "xy", "xz", "yy", "yz", "zz"][c])
+                    errs[key] = float(np.abs(a[:, c] - refa[:, c]).max()
+                                      / np.abs(refa[:, c]).max())
+        out[dt] = {"evals_per_s": npos * NSPL / (ms * 1e-3), "us_per_launch": ms * 1e3,
+                   "hbm_gbs": A.batch_bytes("vgh", dt, npos, NSPL) / (ms * 1e-3) / 1e9,
+                   "max_norm_err": max(errs.values()), "err_per_component": errs}
+        if dt != "f32":
+            B.spline_table_destroy(t)
+    for dt in ("f16", "bf16"):
+        out[dt]["speedup_vs_f32"] = out[dt]["evals_per_s"] / out["f32"]["evals_per_s"]
+    out["npos"] = npos
+    return out
+
+
+def cpu_baseline(np, synth, coef, budget_cpu_s=12.0, max_batches=64):
+    """The FP64 oracle on the host cores, on 512-position batches of the same
+    workload until about budget_cpu_s CPU-seconds have been spent."""
+    import oracle
+    nth = oracle.num_threads()
+    done, wall = 0, 0.0
+    b = 0
+    while b < max_batches and wall * nth < budget_cpu_s:
+        pos = synth.positions(NPOS, stream=synth.position_stream(0), batch=b)
+        t = time.perf_counter()
+        oracle.evaluate("vgh", coef, pos)
+        wall += time.perf_counter() - t
+        done += NPOS
+        b += 1
+    cpu = platform.processor() or platform.machine()
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": done * NSPL / wall, "unit": "orbital-evals/s", "cores": nth,
+            "kind": "oracle",
+            "sample": f"eval_vgh FP64 oracle (C, OpenMP over positions), {b} batches x "
+                      f"{NPOS} positions x N={NSPL} of the same 48^3 table, {wall:.2f} s wall",
+            "cpu_model": cpu, "nproc": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -52,19 +52,32 @@ def component(arr_dict, key, k):
     return a if k is None else a[:, k]
 
 
-def normalized_errors(kind, gpu, ref):
-    """Per component: max |gpu - ref| / max |ref| over all positions and splines."""
+ORDER = {"v": 0, "g": 1, "l": 2, "h": 2}
+
+
+def normalized_errors(kind, gpu, ref, inv_delta=None):
+    """Per component: max |gpu - ref| / max |ref| over all positions and splines.
+
+    A component whose reference vanishes identically (a constant function on
+    a degenerate grid) has no scale of its own; given ``inv_delta`` (the
+    largest n_d / L_d), it is normalised by the natural scale
+    max|V| * inv_delta^order instead."""
     errs = {}
+    vmax = np.abs(ref["v"]).max() if "v" in ref else 0.0
     for key, k in COMPONENTS[kind]:
         r = component(ref, key, k)
         g = component(gpu, key, k)
         scale = np.abs(r).max()
+        if inv_delta is not None:
+            natural = vmax * inv_delta ** ORDER[key]
+            if scale < 1e-6 * natural:
+                scale = natural
         errs[COMP_NAMES[(key, k)]] = float(np.abs(g - r).max() / (scale if scale > 0 else 1.0))
     return errs
 
 
-def assert_close(kind, gpu, ref, tol=FP32_TOL, label=""):
-    errs = normalized_errors(kind, gpu, ref)
+def assert_close(kind, gpu, ref, tol=FP32_TOL, label="", inv_delta=None):
+    errs = normalized_errors(kind, gpu, ref, inv_delta)
     bad = {k: e for k, e in errs.items() if not e <= tol}
     assert not bad, f"{label} normalised errors above {tol}: {bad} (all: {errs})"
     return errs

@@ -173,7 +173,8 @@ def test_shapes(shape):
         for kind in ("v", "vgl", "vgh"):
             gpu, _ = run_gpu(B, t.h, kind, pos, shape[3])
             assert_close(kind, gpu, oracle.evaluate(kind, coef, pos, box=box),
-                         label=f"{shape} {kind}")
+                         label=f"{shape} {kind}",
+                         inv_delta=max(n / b for n, b in zip(shape[:3], box)))
 
 
 def test_unaligned_ldo_and_outputs(cfg1):
@@ -231,17 +232,20 @@ def test_padded_polynomial_reproduction():
                  "g": np.stack([comp(1, 0, 0), comp(0, 1, 0), comp(0, 0, 1)], 1),
                  "h": np.stack([comp(2, 0, 0), comp(1, 1, 0), comp(1, 0, 1), comp(0, 2, 0),
                                 comp(0, 1, 1), comp(0, 0, 2)], 1)}
-        # the table holds FP32 roundings of the exact coefficients
+        # The table holds FP32 roundings of the exact coefficients, and a
+        # component that vanishes (e.g. d2/dy2 of w^3) is a cancellation of
+        # weights summing to zero times values of size max|V|: its error
+        # scale is max|V| / Delta^order.
         scale_v = max(1.0, np.abs(exact["v"]).max())
-        assert np.abs(gpu["v"][:, col] - exact["v"]).max() <= 2e-5 * scale_v, (a, b, c)
+        assert np.abs(gpu["v"][:, col] - exact["v"]).max() <= 1e-5 * scale_v, (a, b, c)
         for k in range(3):
             e = exact["g"][:, k]
-            s = max(1.0 / d.min(), np.abs(e).max())
-            assert np.abs(gpu["g"][:, k, col] - e).max() <= 2e-5 * s, (a, b, c, k)
+            s = max(scale_v / d.min(), np.abs(e).max())
+            assert np.abs(gpu["g"][:, k, col] - e).max() <= 1e-5 * s, (a, b, c, k)
         for k in range(6):
             e = exact["h"][:, k]
-            s = max(1.0 / d.min()**2, np.abs(e).max())
-            assert np.abs(gpu["h"][:, k, col] - e).max() <= 2e-5 * s, (a, b, c, k)
+            s = max(scale_v / d.min()**2, np.abs(e).max())
+            assert np.abs(gpu["h"][:, k, col] - e).max() <= 1e-5 * s, (a, b, c, k)
 
 
 def test_constant_coefficients():
@@ -263,6 +267,7 @@ def test_layout_readback_bit_exact(dtype):
     coef = synth.coef_table(4, 5, 3, 70, stream=41)
     coef[..., 5] = 0.0           # all-zero spline -> scale 1
     coef[..., 6] *= 1e-3         # small spline -> small power-of-two scale
+    coef[..., 7] *= 0.5
     coef[0, 0, 0, 7] = -0.5      # max exactly a power of two
     with Table(coef, dtype) as t:
         info = B.spline_table_info(t.h)
