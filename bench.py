@@ -135,8 +135,9 @@ def main(argv=None):
     l = torch.empty(NPOS, ldo, device=dev)
     pp = [b.data_ptr() for b in batches]
     vp, gp, hp, lp = v.data_ptr(), g.data_ptr(), h.data_ptr(), l.data_ptr()
-    tile = B.spline_tile_select(t32, "vgh", NPOS)
-    log(f"[bench] table ready, tile {tile}")
+    # the autotuner picks the work decomposition (kept in the in-process wisdom)
+    tile = B.spline_autotune(t32, "vgh", NPOS)
+    log(f"[bench] table ready, tuned tile {tile}")
 
     def vgh_step(i):
         B.spline_eval_vgh(t32, NPOS, pp[i % NBATCH], vp, gp, hp, ldo, stream)
@@ -188,13 +189,18 @@ def main(argv=None):
         # VGL on the same table and batches
         def vgl_step(i):
             B.spline_eval_vgl(t32, NPOS, pp[i % NBATCH], vp, gp, lp, ldo, stream)
+        tile_l = B.spline_autotune(t32, "vgl", NPOS)
         ms_l = timed(torch, vgl_step, max(100, steps // 2), warmup)
         extra["vgl"] = {"evals_per_s": evals / (ms_l * 1e-3), "us_per_launch": ms_l * 1e3,
-                        "hbm_gbs": A.batch_bytes("vgl", "f32", NPOS, NSPL) / (ms_l * 1e-3) / 1e9}
+                        "hbm_gbs": A.batch_bytes("vgl", "f32", NPOS, NSPL) / (ms_l * 1e-3) / 1e9,
+                        "tile": list(tile_l.as_tuple())}
         copy_gbs, _ = copy_probe(torch)
         extra["copy_gbs_measured"] = copy_gbs
         line["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
         extra["precision"] = precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup)
+        log("[bench] precision extra done")
+        extra["batched"] = batched_extra(torch, B, A, synth, steps, warmup)
+        log("[bench] batched extra done")
         line["extra"] = extra
 
     B.spline_table_destroy(t32)
@@ -224,9 +230,18 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
     k = max(50, steps // 8)
     for dt in ("f32", "f16", "bf16"):
         t = t32 if dt == "f32" else B.spline_table_create(*GRID, NSPL, coef, dt)
+        tile = B.spline_autotune(t, "vgh", npos)
         ms = timed(torch, lambda i: B.spline_eval_vgh(t, npos, pp[i % nb], v.data_ptr(),
                                                       g.data_ptr(), h.data_ptr(), NSPL, stream),
                    k, warmup)
+        # the batched form: the same work as one persistent launch replayed
+        # from a HIP graph (the plan's tile comes from its own autotuning)
+        plans = [B.spline_batch_plan_create([t], [npos], "vgh", [batches[b]], [v], [g], [h],
+                                            [NSPL], stream=stream) for b in range(nb)]
+        ms_b = timed(torch, lambda i: B.spline_batch_execute(plans[i % nb], stream), k, warmup)
+        ptile = B.spline_batch_plan_tile(plans[0])
+        for pl in plans:
+            B.spline_batch_plan_destroy(pl)
         # error on the first 64 positions of batch 0 vs the FP64 oracle
         B.spline_eval_vgh(t, 64, sample_d.data_ptr(), v.data_ptr(), g.data_ptr(), h.data_ptr(),
                           NSPL, stream)
@@ -245,13 +260,64 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
                                       / np.abs(refa[:, c]).max())
         out[dt] = {"evals_per_s": npos * NSPL / (ms * 1e-3), "us_per_launch": ms * 1e3,
                    "hbm_gbs": A.batch_bytes("vgh", dt, npos, NSPL) / (ms * 1e-3) / 1e9,
+                   "tile": list(tile.as_tuple()),
+                   "batched_evals_per_s": npos * NSPL / (ms_b * 1e-3),
+                   "batched_us_per_launch": ms_b * 1e3, "batched_tile": list(ptile.as_tuple()),
                    "max_norm_err": max(errs.values()), "err_per_component": errs}
         if dt != "f32":
             B.spline_table_destroy(t)
     for dt in ("f16", "bf16"):
         out[dt]["speedup_vs_f32"] = out[dt]["evals_per_s"] / out["f32"]["evals_per_s"]
+        out[dt]["batched_speedup_vs_f32"] = (out[dt]["batched_evals_per_s"]
+                                             / out["f32"]["batched_evals_per_s"])
     out["npos"] = npos
+    out["workload"] = ("eval_vgh on the same 48^3 x N=2048 coefficients stored as FP32, FP16 "
+                       "and BF16 (per-spline FP32 scales), 4096 uniform positions per batch, "
+                       "4 batches cycled; errors on 64 positions vs the FP64 oracle, "
+                       "normalised per component by max|reference|")
     return out
+
+
+CFG4 = [((32, 32, 32), 256, 97), ((40, 40, 40), 512, 512), ((48, 48, 48), 1152, 1500),
+        ((64, 64, 64), 2048, 3000)]
+
+
+def batched_extra(torch, B, A, synth, steps, warmup):
+    """Four tables of uneven shape and batch size in one persistent launch
+    replayed from a HIP graph, FP32 and FP16 tables."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    coefs = [synth.coef_table(*grid, n, stream=synth.table_stream(i))
+             for i, (grid, n, _) in enumerate(CFG4)]
+    npos = [c[2] for c in CFG4]
+    nb = 2
+    pos = [[torch.from_numpy(synth.positions(m, stream=synth.position_stream(i), batch=b))
+            .to(dev) for i, m in enumerate(npos)] for b in range(nb)]
+    outs = [(torch.empty(m, n, device=dev), torch.empty(m, 3, n, device=dev),
+             torch.empty(m, 6, n, device=dev)) for (_, n, m) in CFG4]
+    evals = sum(n * m for (_, n, m) in CFG4)
+    res = {"evals_per_replay": evals,
+           "workload": "eval_vgh, tables 32^3xN=256, 40^3xN=512, 48^3xN=1152, 64^3xN=2048 "
+                       "with 97/512/1500/3000 uniform positions, one persistent launch per "
+                       "replay, 2 position sets alternated"}
+    for dt in ("f32", "f16"):
+        tabs = [B.spline_table_create(*grid, n, c, dt) for (grid, n, _), c in zip(CFG4, coefs)]
+        plans = [B.spline_batch_plan_create(tabs, npos, "vgh", pos[b], [o[0] for o in outs],
+                                            [o[1] for o in outs], [o[2] for o in outs],
+                                            [n for (_, n, _) in CFG4], stream=stream)
+                 for b in range(nb)]
+        ms = timed(torch, lambda i: B.spline_batch_execute(plans[i % nb], stream),
+                   max(50, steps // 10), warmup)
+        alg = sum(A.batch_bytes("vgh", dt, m, n) for (_, n, m) in CFG4)
+        res[dt] = {"evals_per_s": evals / (ms * 1e-3), "us_per_replay": ms * 1e3,
+                   "hbm_gbs": alg / (ms * 1e-3) / 1e9,
+                   "tile": list(B.spline_batch_plan_tile(plans[0]).as_tuple())}
+        for pl in plans:
+            B.spline_batch_plan_destroy(pl)
+        for t in tabs:
+            B.spline_table_destroy(t)
+    res["f16_speedup_vs_f32"] = res["f16"]["evals_per_s"] / res["f32"]["evals_per_s"]
+    return res
 
 
 def cpu_baseline(np, synth, coef, budget_cpu_s=12.0, max_batches=64):
