@@ -201,6 +201,8 @@ def main(argv=None):
         log("[bench] precision extra done")
         extra["batched"] = batched_extra(torch, B, A, synth, steps, warmup)
         log("[bench] batched extra done")
+        extra["large"] = large_extra(torch, B, A, synth, warmup)
+        log("[bench] large-table extra done")
         line["extra"] = extra
 
     B.spline_table_destroy(t32)
@@ -317,6 +319,42 @@ def batched_extra(torch, B, A, synth, steps, warmup):
         for t in tabs:
             B.spline_table_destroy(t)
     res["f16_speedup_vs_f32"] = res["f16"]["evals_per_s"] / res["f32"]["evals_per_s"]
+    return res
+
+
+def large_extra(torch, B, A, synth, warmup):
+    """96^3 (99^3 padded) x N=4096 tables beyond the Infinity Cache: FP32
+    (15.9 GB) and FP16 (7.9 GB), 8192 positions per batch, VGH and VGL."""
+    grid, n, npos = (96, 96, 96), 4096, 8192
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    src = synth.coef_table_torch(torch, *grid, n, device=dev, stream=synth.table_stream(0))
+    tabs = {dt: B.spline_table_create(*grid, n, src, dt, flags=B.BSPL_COEFS_DEVICE)
+            for dt in ("f32", "f16")}
+    del src
+    torch.cuda.empty_cache()
+    nb = 2
+    pos = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0), batch=b))
+           .to(dev) for b in range(nb)]
+    v = torch.empty(npos, n, device=dev)
+    g = torch.empty(npos, 3, n, device=dev)
+    lh = torch.empty(npos, 6, n, device=dev)
+    res = {"workload": "96^3 (99^3 padded) x N=4096 table, FP32 15.9 GB / FP16 7.9 GB, "
+                       "8192 uniform positions per batch, 2 batches alternated"}
+    for dt, t in tabs.items():
+        for kind in ("vgh", "vgl"):
+            tile = B.spline_autotune(t, kind, npos)
+            ms = timed(torch, lambda i: B.spline_eval(t, kind, npos, pos[i % nb], v, g, lh, n,
+                                                      stream=stream), 20, min(warmup, 5))
+            res[f"{dt}_{kind}"] = {
+                "evals_per_s": npos * n / (ms * 1e-3), "ms_per_launch": ms,
+                "hbm_gbs": A.batch_bytes(kind, dt, npos, n) / (ms * 1e-3) / 1e9,
+                "tile": list(tile.as_tuple())}
+    for kind in ("vgh", "vgl"):
+        res[f"f16_speedup_{kind}"] = (res[f"f16_{kind}"]["evals_per_s"]
+                                      / res[f"f32_{kind}"]["evals_per_s"])
+    for t in tabs.values():
+        B.spline_table_destroy(t)
     return res
 
 

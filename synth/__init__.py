@@ -119,3 +119,41 @@ def table_stream(t: int) -> int:
 
 def position_stream(t: int) -> int:
     return 2 * t + 1
+
+
+# --------------------------------------------------------------------------
+# The same generator with torch integer ops, so that very large tables can be
+# drawn directly in device memory.  Bit-identical to the numpy version (the
+# arithmetic is modulo 2**64 in both; shifts are made logical by masking).
+
+def _i64(u: int) -> int:
+    u &= (1 << 64) - 1
+    return u - (1 << 64) if u >= 1 << 63 else u
+
+
+def _lsr(torch, z, s: int):
+    return (z >> s) & ((1 << (64 - s)) - 1)
+
+
+def mix64_torch(torch, z):
+    z = (z ^ _lsr(torch, z, 30)) * _i64(0xBF58476D1CE4E5B9)
+    z = (z ^ _lsr(torch, z, 27)) * _i64(0x94D049BB133111EB)
+    return z ^ _lsr(torch, z, 31)
+
+
+def coef_table_torch(torch, nx: int, ny: int, nz: int, nsplines: int, *, device,
+                     seed: int = SEED, stream: int = 0, chunk: int = 1 << 26):
+    """Unpadded ``[nx][ny][nz][N]`` FP32 table drawn on ``device``; equal bit
+    for bit to :func:`coef_table`."""
+    key = _i64(int(stream_key(seed, stream)))
+    gamma = _i64(0x9E3779B97F4A7C15)
+    total = nx * ny * nz * nsplines
+    out = torch.empty(total, dtype=torch.float32, device=device)
+    for i0 in range(0, total, chunk):
+        i1 = min(total, i0 + chunk)
+        idx = torch.arange(i0 + 1, i1 + 1, dtype=torch.int64, device=device)
+        h = mix64_torch(torch, idx * gamma + key)
+        k = _lsr(torch, h, 40)
+        out[i0:i1] = (2 * k + 1 - (1 << 24)).to(torch.float64).mul_(2.0 ** -24).to(torch.float32)
+        del idx, h, k
+    return out.view(nx, ny, nz, nsplines)

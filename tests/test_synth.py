@@ -42,3 +42,10 @@ def test_positions_uniform_and_batches_differ():
     np.testing.assert_array_equal(p0, synth.positions(4096, batch=0))
     pb = synth.positions(100, box=(2.0, 3.0, 0.5))
     np.testing.assert_array_equal(pb[1], synth.positions(100)[1] * 3.0)
+
+
+def test_torch_generator_matches_numpy_on_cpu():
+    torch = __import__("pytest").importorskip("torch")
+    a = synth.coef_table(6, 5, 7, 45, stream=6)
+    b = synth.coef_table_torch(torch, 6, 5, 7, 45, device="cpu", stream=6, chunk=777)
+    np.testing.assert_array_equal(a, b.numpy())
