@@ -90,14 +90,20 @@ typedef struct {
  * position and 64*vw consecutive splines at a time ("spline tile", the GPU
  * counterpart of the paper's AoSoA tile N_b, section "Optimizations and
  * Parallelization").  A workgroup holds wx tiles of the same positions
- * side by side and wy positions: wx*wy wavefronts, at most 16.  grid = 0
+ * side by side and wy positions: wx*wy wavefronts, at most 8.  grid = 0
  * launches one workgroup per (wx tiles x wy positions) block; grid > 0
- * launches that many persistent workgroups that loop over the blocks.    */
+ * launches that many persistent workgroups that loop over the blocks.
+ * order = 1 first sorts the positions by the Morton code of their grid cell
+ * (in chunks of 4096, on the device, in stream-ordered scratch memory) so
+ * that positions sharing table rows are evaluated together; order = 2 also
+ * hands each of the 8 XCDs a contiguous run of the sorted blocks.  The
+ * order changes no result: every output is computed the same way.        */
 typedef struct {
-    int32_t vw;   /* splines per lane: 1, 2, 4 (F32) or 2, 4, 8 (F16/BF16) */
-    int32_t wx;   /* wavefronts per workgroup along splines */
-    int32_t wy;   /* wavefronts per workgroup along positions */
-    int32_t grid; /* persistent workgroups, or 0 */
+    int32_t vw;    /* splines per lane: 1, 2, 4 (F32) or 2, 4, 8 (F16/BF16) */
+    int32_t wx;    /* wavefronts per workgroup along splines */
+    int32_t wy;    /* wavefronts per workgroup along positions */
+    int32_t grid;  /* persistent workgroups, or 0 */
+    int32_t order; /* 0 input order, 1 cell-sorted, 2 cell-sorted + XCD-grouped */
 } bspl_tile;
 
 /* Human-readable name of a status code (static string). */

@@ -55,7 +55,8 @@ int64_t pow2_bucket(int64_t n) {
 bool parse_line(const char* line, std::string* key, bspl_tile* t) {
     char k[256];
     bspl_tile x{};
-    if (sscanf(line, "%255s %d %d %d %d", k, &x.vw, &x.wx, &x.wy, &x.grid) != 5) return false;
+    if (sscanf(line, "%255s %d %d %d %d %d", k, &x.vw, &x.wx, &x.wy, &x.grid, &x.order) != 6)
+        return false;
     *key = k;
     *t = x;
     return true;
@@ -118,10 +119,9 @@ std::vector<bspl_tile> tile_candidates(int dtype, int64_t max_nsplines, bool per
             if (s[0] > chunks && s[0] > 1) continue;
             const int* grids = persistent ? grids_p : grids_s;
             const int ng = persistent ? 5 : 1;
-            for (int gi = 0; gi < ng; ++gi) {
-                bspl_tile t{vw, s[0], s[1], grids[gi] * cus};
-                out.push_back(t);
-            }
+            for (int gi = 0; gi < ng; ++gi)
+                for (int order = 0; order <= 2; ++order)
+                    out.push_back(bspl_tile{vw, s[0], s[1], grids[gi] * cus, order});
         }
     }
     return out;
@@ -196,7 +196,7 @@ static bspl_status append_wisdom(const char* path, const char* key, const bspl_t
                                  float us) {
     FILE* f = fopen(path, "a");
     if (!f) return fail(BSPL_EIO, "cannot append to wisdom file %s", path);
-    fprintf(f, "%s %d %d %d %d %.3f\n", key, t.vw, t.wx, t.wy, t.grid, us);
+    fprintf(f, "%s %d %d %d %d %d %.3f\n", key, t.vw, t.wx, t.wy, t.grid, t.order, us);
     const bool ok = fclose(f) == 0;
     return ok ? BSPL_OK : fail(BSPL_EIO, "cannot write wisdom file %s", path);
 }
@@ -224,11 +224,8 @@ struct SingleCtx {
 
 bspl_status run_single(void* vctx, const bspl_tile& tile, int it) {
     SingleCtx* c = static_cast<SingleCtx*>(vctx);
-    TableDesc d;
-    bspl_status st = make_desc(c->t, c->npos, c->pos[it & 3], c->out[0], c->out[1], c->out[2],
-                               c->ldo, tile.vw, tile.wx, tile.wy, &d);
-    if (st != BSPL_OK) return st;
-    return launch_single(c->t, c->kind, d, tile, c->s);
+    return spline_eval(c->t, static_cast<bspl_kind>(c->kind), c->npos, c->pos[it & 3],
+                       c->out[0], c->out[1], c->out[2], c->ldo, &tile, c->s);
 }
 
 }  // namespace
@@ -304,8 +301,8 @@ bspl_status spline_wisdom_save(const char* path) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         for (auto& kv : cache())
-            fprintf(f, "%s %d %d %d %d\n", kv.first.c_str(), kv.second.vw, kv.second.wx,
-                    kv.second.wy, kv.second.grid);
+            fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.vw, kv.second.wx,
+                    kv.second.wy, kv.second.grid, kv.second.order);
     }
     return fclose(f) == 0 ? BSPL_OK : fail(BSPL_EIO, "cannot write wisdom file %s", path);
 }

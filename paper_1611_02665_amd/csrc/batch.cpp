@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -26,6 +27,10 @@ struct bspl_plan {
     int64_t npos[bspl::kMaxTables] = {};
     int64_t ldo[bspl::kMaxTables] = {};
     bspl::KernelArgs<bspl::kMaxTables> args{};
+    int32_t* d_perm = nullptr;               // cell orders of all tables (order > 0)
+    int64_t perm_off[bspl::kMaxTables] = {};
+    bspl::OrderLaunch order[bspl::kMaxTables];
+    hipGraphNode_t order_node[bspl::kMaxTables] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node = nullptr;
@@ -46,7 +51,7 @@ struct Bindings {
 };
 
 bspl_status build_args(const bspl_plan& p, const bspl_tile& tile, const Bindings& b,
-                       KernelArgs<kMaxTables>* out) {
+                       KernelArgs<kMaxTables>* out, int32_t* perm_base = nullptr) {
     KernelArgs<kMaxTables> a{};
     int64_t begin = 0;
     for (int i = 0; i < p.ntables; ++i) {
@@ -57,6 +62,7 @@ bspl_status build_args(const bspl_plan& p, const bspl_tile& tile, const Bindings
                                    tile.vw, tile.wx, tile.wy, &d);
         if (st != BSPL_OK) return st;
         d.groups_begin = begin;
+        if (tile.order > 0 && perm_base) d.perm = perm_base + p.perm_off[i];
         begin += (int64_t)d.xgroups * ((p.npos[i] + tile.wy - 1) / tile.wy);
         a.t[i] = d;
     }
@@ -65,6 +71,7 @@ bspl_status build_args(const bspl_plan& p, const bspl_tile& tile, const Bindings
     a.ntables = p.ntables;
     a.wx = tile.wx;
     a.wy = tile.wy;
+    a.xcd_remap = tile.order == 2 ? 1 : 0;
     *out = a;
     return BSPL_OK;
 }
@@ -103,13 +110,18 @@ int64_t grid_for(const KernelArgs<kMaxTables>& a, const bspl_tile& t) {
 struct TuneCtx {
     bspl_plan* p;
     Bindings b[2];
+    int32_t* perm;
     hipStream_t s;
 };
 
 bspl_status run_batch(void* vctx, const bspl_tile& tile, int it) {
     TuneCtx* c = static_cast<TuneCtx*>(vctx);
     KernelArgs<kMaxTables> a;
-    bspl_status st = build_args(*c->p, tile, c->b[it & 1], &a);
+    bspl_status st = build_args(*c->p, tile, c->b[it & 1], &a, c->perm);
+    if (st != BSPL_OK) return st;
+    if (tile.order > 0)
+        for (int i = 0; i < c->p->ntables && st == BSPL_OK; ++i)
+            st = launch_order(a.t[i], const_cast<int32_t*>(a.t[i].perm), c->s);
     if (st != BSPL_OK) return st;
     return launch_multi(c->p->dtype, c->p->kind, a, tile, c->s);
 }
@@ -128,6 +140,7 @@ bspl_status autotune_plan(bspl_plan* p, hipStream_t s, bspl_tile* best, float* u
     TuneCtx c{};
     c.p = p;
     c.s = s;
+    c.perm = p->d_perm;
     char* m = static_cast<char*>(mem);
     bspl_status st = BSPL_OK;
     int64_t max_n = 1;
@@ -163,10 +176,32 @@ bspl_status autotune_plan(bspl_plan* p, hipStream_t s, bspl_tile* best, float* u
     return st;
 }
 
+hipKernelNodeParams order_params(bspl_plan* p, int i) {
+    order_launch_config(p->args.t[i], const_cast<int32_t*>(p->args.t[i].perm), &p->order[i]);
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(order_kernel_ptr());
+    kp.gridDim = dim3(p->order[i].grid);
+    kp.blockDim = dim3(p->order[i].block);
+    kp.sharedMemBytes = p->order[i].shmem;
+    kp.kernelParams = p->order[i].args;
+    kp.extra = nullptr;
+    return kp;
+}
+
+// Graph: [one ordering node per table (order > 0)] -> one evaluation node.
 bspl_status instantiate(bspl_plan* p) {
     const void* fn = multi_kernel_ptr(p->dtype, p->kind, p->tile.vw);
     if (!fn) return fail(BSPL_EINVAL, "no batched kernel for vw=%d", p->tile.vw);
     BSPL_HIP(hipGraphCreate(&p->graph, 0));
+    std::vector<hipGraphNode_t> deps;
+    if (p->tile.order > 0) {
+        for (int i = 0; i < p->ntables; ++i) {
+            if (p->npos[i] == 0) continue;
+            hipKernelNodeParams op = order_params(p, i);
+            BSPL_HIP(hipGraphAddKernelNode(&p->order_node[i], p->graph, nullptr, 0, &op));
+            deps.push_back(p->order_node[i]);
+        }
+    }
     hipKernelNodeParams kp{};
     void* params[] = {&p->args};
     kp.func = const_cast<void*>(fn);
@@ -175,7 +210,8 @@ bspl_status instantiate(bspl_plan* p) {
     kp.sharedMemBytes = 0;
     kp.kernelParams = params;
     kp.extra = nullptr;
-    BSPL_HIP(hipGraphAddKernelNode(&p->node, p->graph, nullptr, 0, &kp));
+    BSPL_HIP(hipGraphAddKernelNode(&p->node, p->graph, deps.empty() ? nullptr : deps.data(),
+                                   deps.size(), &kp));
     BSPL_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     return BSPL_OK;
 }
@@ -234,9 +270,23 @@ bspl_status spline_batch_plan_create(bspl_plan** out, int ntables, const bspl_ta
         b.lh[i] = kind == BSPL_V ? nullptr : lh[i];
     }
     bspl_status st = BSPL_OK;
+    // permutation storage for cell-ordered tiles (allocated up front so the
+    // autotuner can try them; a few bytes per position)
+    int64_t total_pos = 0;
+    for (int i = 0; i < ntables; ++i) {
+        p->perm_off[i] = total_pos;
+        total_pos += (p->npos[i] + 63) / 64 * 64;
+    }
+    if (total_pos > 0) {
+        hipError_t e = hipMalloc((void**)&p->d_perm, sizeof(int32_t) * (size_t)total_pos);
+        if (e != hipSuccess) {
+            delete p;
+            return hip_fail(e, "hipMalloc(permutations)");
+        }
+    }
     if (tile) {
         if (!tile_valid(*tile, p->dtype)) {
-            delete p;
+            spline_batch_plan_destroy(p);
             return fail(BSPL_EINVAL, "tile invalid for dtype");
         }
         p->tile = *tile;
@@ -252,13 +302,13 @@ bspl_status spline_batch_plan_create(bspl_plan** out, int ntables, const bspl_ta
             st = autotune_plan(p, s, &t, &us);
             if (st == BSPL_OK) st = record_wisdom(wisdom_path, key, t, us);
             if (st != BSPL_OK) {
-                delete p;
+                spline_batch_plan_destroy(p);
                 return st;
             }
             p->tile = t;
         }
     }
-    st = build_args(*p, p->tile, b, &p->args);
+    st = build_args(*p, p->tile, b, &p->args, p->d_perm);
     if (st == BSPL_OK) st = instantiate(p);
     if (st != BSPL_OK) {
         spline_batch_plan_destroy(p);
@@ -272,6 +322,13 @@ bspl_status spline_batch_execute(bspl_plan* p, void* stream) {
     if (!p) return fail(BSPL_EINVAL, "plan is NULL");
     if (p->args.total_groups == 0) return BSPL_OK;
     if (p->dirty) {
+        if (p->tile.order > 0) {
+            for (int i = 0; i < p->ntables; ++i) {
+                if (!p->order_node[i]) continue;
+                hipKernelNodeParams op = order_params(p, i);
+                BSPL_HIP(hipGraphExecKernelNodeSetParams(p->exec, p->order_node[i], &op));
+            }
+        }
         hipKernelNodeParams kp{};
         void* params[] = {&p->args};
         kp.func = const_cast<void*>(multi_kernel_ptr(p->dtype, p->kind, p->tile.vw));
@@ -297,7 +354,7 @@ bspl_status spline_batch_rebind(bspl_plan* p, int i, const double* pos, float* v
     b.g[i] = p->kind == BSPL_V ? nullptr : g;
     b.lh[i] = p->kind == BSPL_V ? nullptr : lh;
     KernelArgs<kMaxTables> a;
-    bspl_status st = build_args(*p, p->tile, b, &a);
+    bspl_status st = build_args(*p, p->tile, b, &a, p->d_perm);
     if (st != BSPL_OK) return st;
     p->args = a;
     p->dirty = true;
@@ -314,6 +371,7 @@ bspl_status spline_batch_plan_destroy(bspl_plan* p) {
     if (!p) return BSPL_OK;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->d_perm) (void)hipFree(p->d_perm);
     delete p;
     return BSPL_OK;
 }

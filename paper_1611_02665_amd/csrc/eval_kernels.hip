@@ -363,6 +363,15 @@ __device__ __forceinline__ void eval_unit(const TableDesc& d, int p, int chunk, 
     }
 }
 
+// Block b of a launch runs on XCD b % 8.  With remapping, XCD x takes the
+// contiguous run [x*per, (x+1)*per) of blocks (the tail stays in place), so
+// that neighbouring positions of a cell-sorted order share one L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t total) {
+    const int64_t per = total / kXcds;
+    if (b >= per * kXcds) return b;
+    return (b % kXcds) * per + b / kXcds;
+}
+
 // One launch over one or several tables.  Workgroup-block g covers wx
 // spline tiles by wy positions of one table; blocks are numbered table by
 // table, positions outer, tiles inner.  With fewer workgroups than blocks
@@ -373,7 +382,8 @@ __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int wxi = wave % a.wx;
     const int wyi = wave / a.wx;
-    for (int64_t g = blockIdx.x; g < a.total_groups; g += gridDim.x) {
+    for (int64_t b = blockIdx.x; b < a.total_groups; b += gridDim.x) {
+        const int64_t g = a.xcd_remap ? xcd_block(b, a.total_groups) : b;
         int ti = 0;
         if constexpr (MAXT > 1) {
             for (int k = 1; k < a.ntables; ++k)
@@ -384,8 +394,11 @@ __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
         const int pg = local / d.xgroups;
         const int cg = local - pg * d.xgroups;
         const int chunk = cg * a.wx + wxi;
-        const int p = pg * a.wy + wyi;
-        if (chunk < d.nchunks && p < d.npos) eval_unit<T, VW, KIND>(d, p, chunk, lane);
+        const int q = pg * a.wy + wyi;
+        if (chunk < d.nchunks && q < d.npos) {
+            const int p = d.perm ? __builtin_amdgcn_readfirstlane(d.perm[q]) : q;
+            eval_unit<T, VW, KIND>(d, p, chunk, lane);
+        }
     }
 }
 
@@ -448,6 +461,7 @@ bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
     a.ntables = 1;
     a.wx = tile.wx;
     a.wy = tile.wy;
+    a.xcd_remap = tile.order == 2 ? 1 : 0;
     const int64_t ygroups = (d.npos + tile.wy - 1) / tile.wy;
     a.total_groups = ygroups * d.xgroups;
     return launch<1>(kernel_for<1>(t->info.dtype, kind, tile.vw), a, tile, s);

@@ -19,6 +19,10 @@ namespace bspl {
 
 // Most tables one batched launch can hold.
 constexpr int kMaxTables = 16;
+// Positions sorted together by one workgroup of the ordering pre-pass.
+constexpr int kOrderChunk = 4096;
+// XCDs of an MI355X; workgroups are dispatched to them round-robin.
+constexpr int kXcds = 8;
 
 // Record a failure message for spline_last_error() and return the status.
 bspl_status fail(bspl_status s, const char* fmt, ...);
@@ -38,6 +42,7 @@ struct TableDesc {
     const char* table;        // padded table
     const float* scales;      // per-spline scales (F16/BF16) or nullptr
     const double* pos;        // [3][npos]
+    const int32_t* perm;      // evaluation order of the positions, or nullptr
     float* v;
     float* g;
     float* lh;
@@ -63,6 +68,7 @@ struct KernelArgs {
     int32_t ntables;
     int32_t wx;
     int32_t wy;
+    int32_t xcd_remap;        // give each XCD a contiguous run of blocks
 };
 
 // Fill a descriptor for table t (positions and outputs included).
@@ -80,6 +86,23 @@ bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
                          const bspl_tile& tile, hipStream_t s);
 // Address of the batched kernel for a configuration (graph node building).
 const void* multi_kernel_ptr(int dtype, int kind, int vw);
+
+// Cell-ordering pre-pass (order_kernels.hip): perm[i] for i < npos.
+// OrderLaunch holds the launch shape and the argument values (args[] points
+// into the struct, so it must not be copied after order_launch_config).
+struct OrderLaunch {
+    const double* pos;
+    int npos;
+    double idx, idy, idz;
+    int nx, ny, nz, shift, chunk;
+    int32_t* perm;
+    unsigned grid, block, shmem;
+    void* args[11];
+};
+int order_chunk(int64_t npos);
+void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o);
+bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s);
+const void* order_kernel_ptr();
 
 // Table layout kernels (layout_kernels.hip).
 bspl_status build_table(bspl_table* t, const float* d_coefs, bool padded_input,

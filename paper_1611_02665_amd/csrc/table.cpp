@@ -39,7 +39,8 @@ bool tile_valid(const bspl_tile& tile, int dtype) {
     const bool f32 = dtype == BSPL_F32;
     const bool vw_ok = f32 ? (tile.vw == 1 || tile.vw == 2 || tile.vw == 4)
                            : (tile.vw == 2 || tile.vw == 4 || tile.vw == 8);
-    return vw_ok && tile.wx >= 1 && tile.wy >= 1 && tile.wx * tile.wy <= 8 && tile.grid >= 0;
+    return vw_ok && tile.wx >= 1 && tile.wy >= 1 && tile.wx * tile.wy <= 8 && tile.grid >= 0 &&
+           tile.order >= 0 && tile.order <= 2;
 }
 
 bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos) {
@@ -55,6 +56,7 @@ bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos) {
     tile.wx = (int)std::min<int64_t>(4, chunks);
     tile.wy = std::max(1, 4 / tile.wx);
     tile.grid = 0;
+    tile.order = 0;
     return tile;
 }
 
@@ -69,6 +71,7 @@ bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, floa
     d.table = static_cast<const char*>(t->d_table);
     d.scales = t->d_scales;
     d.pos = pos;
+    d.perm = nullptr;
     d.v = v;
     d.g = g;
     d.lh = lh;
@@ -271,7 +274,19 @@ bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const
     bspl_status st = make_desc(t, npos, pos, v, kind == BSPL_V ? nullptr : g,
                                kind == BSPL_V ? nullptr : lh, ldo, tl.vw, tl.wx, tl.wy, &d);
     if (st != BSPL_OK) return st;
-    return launch_single(t, kind, d, tl, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (tl.order == 0) return launch_single(t, kind, d, tl, s);
+    // cell-ordered: the permutation lives in stream-ordered scratch memory
+    int32_t* perm = nullptr;
+    BSPL_HIP(hipMallocAsync((void**)&perm, sizeof(int32_t) * (size_t)npos, s));
+    st = launch_order(d, perm, s);
+    if (st == BSPL_OK) {
+        d.perm = perm;
+        st = launch_single(t, kind, d, tl, s);
+    }
+    hipError_t e = hipFreeAsync(perm, s);
+    if (st == BSPL_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync(permutation)");
+    return st;
 }
 
 bspl_status spline_eval_v(const bspl_table* t, int64_t npos, const double* pos, float* v,

@@ -92,6 +92,14 @@ def test_create_validates_before_touching_the_device():
         == B.BSPL_EINVAL
 
 
+def test_tile_struct_matches_header():
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {\n    int32_t vw;"):]
+    body = body[:body.index("} bspl_tile;")]
+    fields = re.findall(r"int32_t (\w+);", body)
+    assert fields == [f for f, _ in B.bspl_tile._fields_]
+
+
 def test_null_handles():
     assert B.lib.spline_table_destroy(None) == B.BSPL_OK
     assert B.lib.spline_batch_plan_destroy(None) == B.BSPL_OK
@@ -129,13 +137,13 @@ def test_wisdom_files(tmp_path):
         B.spline_wisdom_load(missing)
     assert e.value.status == B.BSPL_EIO
     p = tmp_path / "w.txt"
-    p.write_text("# comment\nsingle|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 12.5\n"
+    p.write_text("# comment\nsingle|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 1 12.5\n"
                  "garbage line\n")
     B.spline_wisdom_load(str(p))
     out = str(tmp_path / "out.txt")
     B.spline_wisdom_save(out)
     text = open(out).read()
-    assert "single|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0" in text
+    assert "single|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 1" in text
     with pytest.raises(B.BsplineError) as e:
         B.spline_wisdom_save(str(tmp_path / "no" / "such" / "dir.txt"))
     assert e.value.status == B.BSPL_EIO

@@ -58,7 +58,7 @@ SMALL_NPOS = [7, 50, 130, 300]
 
 
 @pytest.mark.parametrize("kind", ["v", "vgl", "vgh"])
-@pytest.mark.parametrize("tile", [(2, 2, 1, 64), (4, 1, 2, 256), (1, 4, 1, 1000)])
+@pytest.mark.parametrize("tile", [(2, 2, 1, 64, 0), (4, 1, 2, 256, 1), (1, 4, 1, 1000, 2)])
 def test_batch_plan_replays(kind, tile):
     T = Tables(SMALL)
     dev = torch.device("cuda")
@@ -142,7 +142,7 @@ def test_batch_plan_rejects_mixed_dtypes():
         v = torch.zeros(4, 32, device=d)
         with pytest.raises(B.BsplineError) as e:
             B.spline_batch_plan_create(a.handles + b.handles, [4, 4], "v", [p, p], [v, v],
-                                       ldo=[32, 32], tile=(1, 1, 1, 8))
+                                       ldo=[32, 32], tile=(1, 1, 1, 8, 0))
         assert e.value.status == B.BSPL_EUNSUPPORTED
     finally:
         a.close()

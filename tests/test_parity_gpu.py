@@ -84,8 +84,8 @@ def test_cross_kind_consistency(cfg1):
 def _tiles(dtype):
     vws = (1, 2, 4) if dtype == "f32" else (2, 4, 8)
     shapes = [(1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (1, 4), (2, 2), (4, 2), (2, 4), (1, 8)]
-    for vw, (wx, wy), grid in itertools.product(vws, shapes, (0, 7)):
-        yield (vw, wx, wy, grid)
+    for i, (vw, (wx, wy), grid) in enumerate(itertools.product(vws, shapes, (0, 7))):
+        yield (vw, wx, wy, grid, i % 3)
 
 
 @pytest.fixture(scope="module")
@@ -114,10 +114,31 @@ def test_all_tiles_ragged(ragged, dtype):
 
 def test_invalid_tiles_rejected(cfg1):
     _, pos, t = cfg1
-    for tile in [(3, 1, 1, 0), (8, 1, 1, 0), (4, 0, 1, 0), (4, 4, 4, 0), (4, 1, 1, -1)]:
+    for tile in [(3, 1, 1, 0, 0), (8, 1, 1, 0, 0), (4, 0, 1, 0, 0), (4, 4, 4, 0, 0),
+                 (4, 1, 1, -1, 0), (4, 1, 1, 0, 3), (4, 1, 1, 0, -1)]:
         with pytest.raises(B.BsplineError) as e:
             run_gpu(B, t.h, "vgh", pos[:, :4], 64, tile=tile)
         assert e.value.status == B.BSPL_EINVAL
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_order_changes_no_result(dtype):
+    """Cell-sorted and XCD-grouped evaluation orders give bit-identical
+    outputs (every output is computed by the same arithmetic)."""
+    coef = synth.coef_table(20, 24, 16, 520, stream=13)
+    pos = synth.positions(5000, stream=14) * 2 - 0.5  # more than one sort chunk
+    with Table(coef, dtype) as t:
+        outs = []
+        for order in (0, 1, 2):
+            for grid in (0, 96):
+                o, raw = run_gpu(B, t.h, "vgh", pos, 520, ldo=520, tile=(2, 2, 2, grid, order))
+                outs.append(raw)
+        for o in outs[1:]:
+            for k in o:
+                assert np.array_equal(o[k], outs[0][k]), k
+        ref = oracle.evaluate("vgh", dequantized(coef, dtype), pos[:, :300])
+        got = {k: a[:300, ..., :520].astype(np.float64) for k, a in outs[-1].items()}
+        assert_close("vgh", got, ref, label=f"ordered {dtype}")
 
 
 # ------------------------------------------------------------ edge cases
