@@ -97,10 +97,16 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--profile", action="store_true", help="headline kernel only")
     ap.add_argument("--copy-probe", action="store_true", help="only a 1 GiB device copy")
+    ap.add_argument("--tile", default=None,
+                    help="profiling: fixed tile vw,wx,wy,grid,order instead of autotuning")
+    ap.add_argument("--npos", type=int, default=NPOS,
+                    help="profiling: positions per batch (the benchmark itself uses 512)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args(argv)
 
+    if args.npos != NPOS and not args.profile:
+        ap.error("--npos is for --profile runs only")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the evaluation "
               "shards by replicating the table and splitting positions, with no "
@@ -126,28 +132,35 @@ def main(argv=None):
     t32 = B.spline_table_create(*GRID, NSPL, coef, "f32")
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
-    batches = [torch.from_numpy(synth.positions(NPOS, stream=synth.position_stream(0), batch=b))
-               .to(dev) for b in range(NBATCH)]
+    npos = args.npos
+    nbatch = NBATCH if npos <= NPOS else 4
+    batches = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0), batch=b))
+               .to(dev) for b in range(nbatch)]
     ldo = NSPL
-    v = torch.empty(NPOS, ldo, device=dev)
-    g = torch.empty(NPOS, 3, ldo, device=dev)
-    h = torch.empty(NPOS, 6, ldo, device=dev)
-    l = torch.empty(NPOS, ldo, device=dev)
+    v = torch.empty(npos, ldo, device=dev)
+    g = torch.empty(npos, 3, ldo, device=dev)
+    h = torch.empty(npos, 6, ldo, device=dev)
+    l = torch.empty(npos, ldo, device=dev)
     pp = [b.data_ptr() for b in batches]
     vp, gp, hp, lp = v.data_ptr(), g.data_ptr(), h.data_ptr(), l.data_ptr()
-    # the autotuner picks the work decomposition (kept in the in-process wisdom)
-    tile = B.spline_autotune(t32, "vgh", NPOS)
-    log(f"[bench] table ready, tuned tile {tile}")
+    if args.tile:
+        tile = B.bspl_tile(*[int(x) for x in args.tile.split(",")])
+    else:
+        # the autotuner picks the work decomposition (kept in the in-process wisdom)
+        tile = B.spline_autotune(t32, "vgh", npos)
+    log(f"[bench] table ready, tile {tile}")
+    tref = B.ctypes.byref(tile)
 
     def vgh_step(i):
-        B.spline_eval_vgh(t32, NPOS, pp[i % NBATCH], vp, gp, hp, ldo, stream)
+        B._check(B.lib.spline_eval(t32, B.BSPL_VGH, npos, pp[i % nbatch], vp, gp, hp, ldo, tref,
+                                   stream), "spline_eval")
 
     steps = 20 if args.profile else args.steps
     warmup = 5 if args.profile else args.warmup
     ms = timed(torch, vgh_step, steps, warmup)
-    evals = NPOS * NSPL
+    evals = npos * NSPL
     value = evals / (ms * 1e-3)
-    alg_bytes = A.batch_bytes("vgh", "f32", NPOS, NSPL)
+    alg_bytes = A.batch_bytes("vgh", "f32", npos, NSPL)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     log(f"[bench] VGH {ms * 1e3:.2f} us/launch, {value:.4g} evals/s, {achieved:.0f} GB/s")
     if args.profile:
@@ -188,7 +201,7 @@ def main(argv=None):
     if not args.no_extras:
         # VGL on the same table and batches
         def vgl_step(i):
-            B.spline_eval_vgl(t32, NPOS, pp[i % NBATCH], vp, gp, lp, ldo, stream)
+            B.spline_eval_vgl(t32, NPOS, pp[i % nbatch], vp, gp, lp, ldo, stream)
         tile_l = B.spline_autotune(t32, "vgl", NPOS)
         ms_l = timed(torch, vgl_step, max(100, steps // 2), warmup)
         extra["vgl"] = {"evals_per_s": evals / (ms_l * 1e-3), "us_per_launch": ms_l * 1e3,
@@ -236,14 +249,14 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
         ms = timed(torch, lambda i: B.spline_eval_vgh(t, npos, pp[i % nb], v.data_ptr(),
                                                       g.data_ptr(), h.data_ptr(), NSPL, stream),
                    k, warmup)
+        # input (random) order only: the paper's access pattern, no row reuse
+        in_tile, ms_in = best_input_order(torch, B, t, dt, npos, pp, nb, v, g, h, stream, warmup)
         # the batched form: the same work as one persistent launch replayed
-        # from a HIP graph (the plan's tile comes from its own autotuning)
-        plans = [B.spline_batch_plan_create([t], [npos], "vgh", [batches[b]], [v], [g], [h],
-                                            [NSPL], stream=stream) for b in range(nb)]
-        ms_b = timed(torch, lambda i: B.spline_batch_execute(plans[i % nb], stream), k, warmup)
-        ptile = B.spline_batch_plan_tile(plans[0])
-        for pl in plans:
-            B.spline_batch_plan_destroy(pl)
+        # from a HIP graph (the plan's tile comes from its own autotuning),
+        # and the same with the best input-order tile on a persistent grid
+        ms_b, ptile = plan_time(torch, B, t, npos, batches, v, g, h, None, stream, k, warmup)
+        ms_bi, _ = plan_time(torch, B, t, npos, batches, v, g, h,
+                             tuple(in_tile[:3]) + (2048, 0), stream, k, warmup)
         # error on the first 64 positions of batch 0 vs the FP64 oracle
         B.spline_eval_vgh(t, 64, sample_d.data_ptr(), v.data_ptr(), g.data_ptr(), h.data_ptr(),
                           NSPL, stream)
@@ -263,21 +276,52 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
         out[dt] = {"evals_per_s": npos * NSPL / (ms * 1e-3), "us_per_launch": ms * 1e3,
                    "hbm_gbs": A.batch_bytes("vgh", dt, npos, NSPL) / (ms * 1e-3) / 1e9,
                    "tile": list(tile.as_tuple()),
+                   "input_order_evals_per_s": npos * NSPL / (ms_in * 1e-3),
+                   "input_order_us_per_launch": ms_in * 1e3, "input_order_tile": list(in_tile),
                    "batched_evals_per_s": npos * NSPL / (ms_b * 1e-3),
                    "batched_us_per_launch": ms_b * 1e3, "batched_tile": list(ptile.as_tuple()),
+                   "batched_input_order_evals_per_s": npos * NSPL / (ms_bi * 1e-3),
                    "max_norm_err": max(errs.values()), "err_per_component": errs}
         if dt != "f32":
             B.spline_table_destroy(t)
     for dt in ("f16", "bf16"):
-        out[dt]["speedup_vs_f32"] = out[dt]["evals_per_s"] / out["f32"]["evals_per_s"]
-        out[dt]["batched_speedup_vs_f32"] = (out[dt]["batched_evals_per_s"]
-                                             / out["f32"]["batched_evals_per_s"])
+        for key in ("evals_per_s", "input_order_evals_per_s", "batched_evals_per_s",
+                    "batched_input_order_evals_per_s"):
+            name = key.replace("evals_per_s", "speedup_vs_f32")
+            out[dt][name] = out[dt][key] / out["f32"][key]
     out["npos"] = npos
     out["workload"] = ("eval_vgh on the same 48^3 x N=2048 coefficients stored as FP32, FP16 "
                        "and BF16 (per-spline FP32 scales), 4096 uniform positions per batch, "
                        "4 batches cycled; errors on 64 positions vs the FP64 oracle, "
                        "normalised per component by max|reference|")
     return out
+
+
+def best_input_order(torch, B, t, dt, npos, pp, nb, v, g, h, stream, warmup):
+    """Fastest input-order (order = 0) tile from a small sweep."""
+    vws = (1, 2, 4) if dt == "f32" else (2, 4, 8)
+    best = None
+    for vw in vws:
+        for wx, wy in ((4, 1), (2, 1), (2, 2), (1, 4)):
+            tile = (vw, wx, wy, 0, 0)
+            ms = timed(torch, lambda i: B.spline_eval(t, "vgh", npos, pp[i % nb], v, g, h, NSPL,
+                                                      tile=tile, stream=stream), 20, 3)
+            if best is None or ms < best[1]:
+                best = (tile, ms)
+    tile = best[0]
+    ms = timed(torch, lambda i: B.spline_eval(t, "vgh", npos, pp[i % nb], v, g, h, NSPL,
+                                              tile=tile, stream=stream), 100, warmup)
+    return tile, ms
+
+
+def plan_time(torch, B, t, npos, batches, v, g, h, tile, stream, k, warmup):
+    plans = [B.spline_batch_plan_create([t], [npos], "vgh", [b], [v], [g], [h], [NSPL],
+                                        tile=tile, stream=stream) for b in batches]
+    ms = timed(torch, lambda i: B.spline_batch_execute(plans[i % len(plans)], stream), k, warmup)
+    ptile = B.spline_batch_plan_tile(plans[0])
+    for pl in plans:
+        B.spline_batch_plan_destroy(pl)
+    return ms, ptile
 
 
 CFG4 = [((32, 32, 32), 256, 97), ((40, 40, 40), 512, 512), ((48, 48, 48), 1152, 1500),

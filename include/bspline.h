@@ -93,11 +93,12 @@ typedef struct {
  * side by side and wy positions: wx*wy wavefronts, at most 8.  grid = 0
  * launches one workgroup per (wx tiles x wy positions) block; grid > 0
  * launches that many persistent workgroups that loop over the blocks.
- * order = 1 first sorts the positions by the Morton code of their grid cell
- * (in chunks of 4096, on the device, in stream-ordered scratch memory) so
- * that positions sharing table rows are evaluated together; order = 2 also
- * hands each of the 8 XCDs a contiguous run of the sorted blocks.  The
- * order changes no result: every output is computed the same way.        */
+ * order = 1 first groups the positions by the Morton code of their cell on
+ * a 16x16x16 coarsening of the grid (a counting sort per chunk of 4096
+ * positions, on the device, in stream-ordered scratch memory) so that
+ * positions sharing table rows are evaluated together; order = 2 also hands
+ * each of the 8 XCDs a contiguous run of the ordered blocks.  The order
+ * changes no result: every output is computed the same way.              */
 typedef struct {
     int32_t vw;    /* splines per lane: 1, 2, 4 (F32) or 2, 4, 8 (F16/BF16) */
     int32_t wx;    /* wavefronts per workgroup along splines */

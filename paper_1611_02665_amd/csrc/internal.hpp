@@ -19,7 +19,7 @@ namespace bspl {
 
 // Most tables one batched launch can hold.
 constexpr int kMaxTables = 16;
-// Positions sorted together by one workgroup of the ordering pre-pass.
+// Positions ordered together by one workgroup of the ordering pre-pass.
 constexpr int kOrderChunk = 4096;
 // XCDs of an MI355X; workgroups are dispatched to them round-robin.
 constexpr int kXcds = 8;
@@ -94,12 +94,11 @@ struct OrderLaunch {
     const double* pos;
     int npos;
     double idx, idy, idz;
-    int nx, ny, nz, shift, chunk;
+    int nx, ny, nz;
     int32_t* perm;
     unsigned grid, block, shmem;
-    void* args[11];
+    void* args[9];
 };
-int order_chunk(int64_t npos);
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o);
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s);
 const void* order_kernel_ptr();

@@ -1,5 +1,5 @@
-// Cell-ordered evaluation: a permutation of the positions sorted by the
-// Morton code of their grid cell.
+// Cell-ordered evaluation: a permutation of the positions grouped by the
+// Morton code of their cell at 16 x 16 x 16 resolution.
 //
 // Positions that are close in space read many of the same table rows (a
 // cell's 64 rows overlap those of every cell within +-3 in each dimension).
@@ -8,80 +8,104 @@
 // perm[logical index] and still write each output at the caller's index, so
 // results do not depend on the order.
 //
-// Each workgroup sorts one chunk of up to kOrderChunk consecutive positions
-// with a bitonic sort of (key << 32 | index) pairs in LDS.
+// One workgroup orders one chunk of up to kOrderChunk consecutive positions
+// with a counting sort: an LDS histogram over the 4096 Morton bins (the
+// atomic's return value is the position's slot in its bin), an exclusive
+// scan of the histogram, and a scatter.  The order inside a bin is whatever
+// the atomics gave; it affects speed only.
 #include "internal.hpp"
 
 namespace bspl {
 namespace {
 
-__device__ __forceinline__ uint32_t spread3(uint32_t v) {  // 10 bits -> every third bit
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000ffu;
-    v = (v | (v << 8)) & 0x0300f00fu;
-    v = (v | (v << 4)) & 0x030c30c3u;
-    v = (v | (v << 2)) & 0x09249249u;
+constexpr int kBins = 4096;        // 16^3 Morton bins
+constexpr int kOrderThreads = 1024;
+constexpr int kPerThread = kOrderChunk / kOrderThreads;
+
+__device__ __forceinline__ uint32_t spread3_4(uint32_t v) {  // 4 bits -> every third bit
+    v &= 0xfu;
+    v = (v | (v << 4)) & 0x0c3u;
+    v = (v | (v << 2)) & 0x249u;
     return v;
 }
 
-// Cell coordinate of x in [0, n) at 10-bit resolution (non-finite -> 0).
-__device__ __forceinline__ uint32_t cell10(double x, double inv_delta, int n, int shift) {
+// Bin coordinate (0..15) of coordinate x on a periodic axis of n cells.
+__device__ __forceinline__ uint32_t bin16(double x, double inv_delta, int n) {
     const double u = x * inv_delta;
     if (!__builtin_isfinite(u) || !(__builtin_fabs(u) < 1125899906842624.0)) return 0u;
     const double nd = (double)n;
-    double w = u - nd * __builtin_floor(u / nd);
-    int i = (int)__builtin_floor(w);
-    i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
-    return (uint32_t)i >> shift;
+    const double w = u - nd * __builtin_floor(u / nd);
+    int b = (int)(w * (16.0 / nd));
+    return (uint32_t)(b < 0 ? 0 : (b > 15 ? 15 : b));
 }
 
-__global__ void __launch_bounds__(1024) order_kernel(const double* __restrict__ pos, int npos,
-                                                     double idx_, double idy_, double idz_,
-                                                     int nx, int ny, int nz, int shift,
-                                                     int chunk, int32_t* __restrict__ perm) {
-    extern __shared__ unsigned long long keys[];
-    const int base = blockIdx.x * chunk;
-    const int cnt = min(chunk, npos - base);
-    for (int i = threadIdx.x; i < chunk; i += blockDim.x) {
-        unsigned long long k = ~0ull;
+__global__ void __launch_bounds__(kOrderThreads) order_kernel(
+    const double* __restrict__ pos, int npos, double idx_, double idy_, double idz_, int nx,
+    int ny, int nz, int32_t* __restrict__ perm) {
+    __shared__ uint32_t count[kBins];
+    __shared__ uint32_t wsum[kOrderThreads / 64];
+    const int tid = threadIdx.x;
+    const int base = blockIdx.x * kOrderChunk;
+    const int cnt = min(kOrderChunk, npos - base);
+    for (int b = tid; b < kBins; b += kOrderThreads) count[b] = 0u;
+    __syncthreads();
+    // bins first (all position loads in flight together), then the
+    // histogram; the atomic's return value is the position's slot in its bin
+    uint32_t bin[kPerThread], slot[kPerThread];
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int i = r * kOrderThreads + tid;
+        bin[r] = 0u;
         if (i < cnt) {
             const int p = base + i;
-            const uint32_t cx = cell10(pos[p], idx_, nx, shift);
-            const uint32_t cy = cell10(pos[(int64_t)npos + p], idy_, ny, shift);
-            const uint32_t cz = cell10(pos[2 * (int64_t)npos + p], idz_, nz, shift);
-            const uint32_t m = (spread3(cx) << 2) | (spread3(cy) << 1) | spread3(cz);
-            k = ((unsigned long long)m << 32) | (uint32_t)i;
+            const uint32_t bx = bin16(pos[p], idx_, nx);
+            const uint32_t by = bin16(pos[(int64_t)npos + p], idy_, ny);
+            const uint32_t bz = bin16(pos[2 * (int64_t)npos + p], idz_, nz);
+            bin[r] = (spread3_4(bx) << 2) | (spread3_4(by) << 1) | spread3_4(bz);
         }
-        keys[i] = k;
+    }
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int i = r * kOrderThreads + tid;
+        slot[r] = i < cnt ? atomicAdd(&count[bin[r]], 1u) : 0u;
     }
     __syncthreads();
-    for (int k = 2; k <= chunk; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < chunk; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const unsigned long long a = keys[i], b = keys[l];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) {
-                        keys[i] = b;
-                        keys[l] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    // exclusive scan over the bins: thread t owns bins [4t, 4t+4)
+    constexpr int kBinsPerThread = kBins / kOrderThreads;
+    uint32_t local[kBinsPerThread];
+    uint32_t run = 0;
+#pragma unroll
+    for (int k = 0; k < kBinsPerThread; ++k) {
+        local[k] = run;
+        run += count[tid * kBinsPerThread + k];
     }
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x)
-        perm[base + i] = base + (int32_t)(keys[i] & 0xffffffffull);
+    // inclusive scan of the per-thread totals: within the wavefront, then
+    // across the 16 wavefronts
+    const int lane = tid & 63, wave = tid >> 6;
+    uint32_t incl = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t wave_base = 0;
+    for (int w = 0; w < wave; ++w) wave_base += wsum[w];
+    const uint32_t excl = wave_base + incl - run;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kBinsPerThread; ++k) count[tid * kBinsPerThread + k] = excl + local[k];
+    __syncthreads();
+    // scatter: logical slot -> caller's index
+#pragma unroll
+    for (int r = 0; r < kPerThread; ++r) {
+        const int i = r * kOrderThreads + tid;
+        if (i < cnt) perm[base + (int)(count[bin[r]] + slot[r])] = base + i;
+    }
 }
 
 }  // namespace
-
-int order_chunk(int64_t npos) {
-    int c = 64;
-    while (c < npos && c < kOrderChunk) c <<= 1;
-    return c;
-}
 
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o) {
     o->pos = d.pos;
@@ -92,19 +116,12 @@ void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o) {
     o->nx = d.ncell[0];
     o->ny = d.ncell[1];
     o->nz = d.ncell[2];
-    int maxn = d.ncell[0];
-    if (d.ncell[1] > maxn) maxn = d.ncell[1];
-    if (d.ncell[2] > maxn) maxn = d.ncell[2];
-    o->shift = 0;
-    while ((maxn - 1) >> o->shift >= 1024) ++o->shift;
-    o->chunk = order_chunk(d.npos);
     o->perm = perm;
-    o->grid = (unsigned)((d.npos + o->chunk - 1) / o->chunk);
-    o->block = o->chunk < 2048 ? (unsigned)o->chunk / 2 : 1024u;
-    o->shmem = (unsigned)(sizeof(unsigned long long) * o->chunk);
-    void* a[] = {&o->pos, &o->npos, &o->idx, &o->idy, &o->idz, &o->nx, &o->ny, &o->nz,
-                 &o->shift, &o->chunk, &o->perm};
-    for (int i = 0; i < 11; ++i) o->args[i] = a[i];
+    o->grid = (unsigned)((d.npos + kOrderChunk - 1) / kOrderChunk);
+    o->block = kOrderThreads;
+    o->shmem = 0;
+    void* a[] = {&o->pos, &o->npos, &o->idx, &o->idy, &o->idz, &o->nx, &o->ny, &o->nz, &o->perm};
+    for (int i = 0; i < 9; ++i) o->args[i] = a[i];
 }
 
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s) {

@@ -126,7 +126,7 @@ def test_order_changes_no_result(dtype):
     """Cell-sorted and XCD-grouped evaluation orders give bit-identical
     outputs (every output is computed by the same arithmetic)."""
     coef = synth.coef_table(20, 24, 16, 520, stream=13)
-    pos = synth.positions(5000, stream=14) * 2 - 0.5  # more than one sort chunk
+    pos = synth.positions(9000, stream=14) * 2 - 0.5  # more than one ordering chunk
     with Table(coef, dtype) as t:
         outs = []
         for order in (0, 1, 2):
