@@ -9,8 +9,9 @@ from the Infinity Cache.  Inputs and outputs stay resident in HBM.
 Printed: one JSON line with value = VGH orbital-evals/s (npos * N / time),
 the HBM roofline of the kernel (algorithmic bytes 64*4 + 10*4 per eval),
 the FP64 oracle timed on the host cores as cpu_baseline, and extras: VGL on
-the same table, and FP16/BF16 tables against FP32 at 4096 positions with
-their error against the oracle.
+the same table, FP16/BF16 tables against FP32 at 4096 positions (with their
+deviation from the FP32-table outputs), the four-table batched workload and
+the 96^3 x 4096 tables.
 
 Modes for profiling: --profile (headline kernel only, few steps),
 --copy-probe (a plain device copy of known size, to scale HBM counters).
@@ -226,8 +227,11 @@ def main(argv=None):
 
 
 def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
-    """FP16 and BF16 tables vs FP32 on the same 4096-position batches."""
-    import oracle  # error check of the reduced-precision tables (test use of the oracle)
+    """FP16 and BF16 tables vs FP32 on the same 4096-position batches.
+
+    Errors here are against the FP32-table GPU outputs on 64 positions (the
+    FP32 table itself matches the FP64 oracle to ~3e-7; the errors against
+    the oracle are checked and printed by the GPU tests)."""
     npos = 4096
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
@@ -240,8 +244,8 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
     h = torch.empty(npos, 6, NSPL, device=dev)
     out = {}
     sample = synth.positions(64, stream=synth.position_stream(0), batch=100)
-    ref = oracle.evaluate("vgh", coef, sample)
     sample_d = torch.from_numpy(sample).to(dev)  # [3][64]: npos is also the row stride
+    ref = None
     k = max(50, steps // 8)
     for dt in ("f32", "f16", "bf16"):
         t = t32 if dt == "f32" else B.spline_table_create(*GRID, NSPL, coef, dt)
@@ -257,22 +261,25 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
         ms_b, ptile = plan_time(torch, B, t, npos, batches, v, g, h, None, stream, k, warmup)
         ms_bi, _ = plan_time(torch, B, t, npos, batches, v, g, h,
                              tuple(in_tile[:3]) + (2048, 0), stream, k, warmup)
-        # error on the first 64 positions of batch 0 vs the FP64 oracle
+        # error on 64 positions against the FP32-table outputs
         B.spline_eval_vgh(t, 64, sample_d.data_ptr(), v.data_ptr(), g.data_ptr(), h.data_ptr(),
                           NSPL, stream)
         torch.cuda.synchronize()
+        got = {"v": v[:64].cpu().numpy().astype(np.float64),
+               "g": g[:64].cpu().numpy().astype(np.float64),
+               "h": h[:64].cpu().numpy().astype(np.float64)}
+        if ref is None:
+            ref = got
         errs = {}
-        for name, arr, refa in (("v", v[:64], ref["v"]), ("g", g[:64], ref["g"]),
-                                ("h", h[:64], ref["h"])):
-            a = arr.cpu().numpy().astype(np.float64)
-            if refa.ndim == 2:
-                errs[name] = float(np.abs(a - refa).max() / np.abs(refa).max())
+        for name in ("v", "g", "h"):
+            a, r = got[name], ref[name]
+            if r.ndim == 2:
+                errs[name] = float(np.abs(a - r).max() / np.abs(r).max())
             else:
-                for c in range(refa.shape[1]):
+                for c in range(r.shape[1]):
                     key = name + ("xyz"[c] if name == "g" else
                                   ["xx", "xy", "xz", "yy", "yz", "zz"][c])
-                    errs[key] = float(np.abs(a[:, c] - refa[:, c]).max()
-                                      / np.abs(refa[:, c]).max())
+                    errs[key] = float(np.abs(a[:, c] - r[:, c]).max() / np.abs(r[:, c]).max())
         out[dt] = {"evals_per_s": npos * NSPL / (ms * 1e-3), "us_per_launch": ms * 1e3,
                    "hbm_gbs": A.batch_bytes("vgh", dt, npos, NSPL) / (ms * 1e-3) / 1e9,
                    "tile": list(tile.as_tuple()),
@@ -281,7 +288,8 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
                    "batched_evals_per_s": npos * NSPL / (ms_b * 1e-3),
                    "batched_us_per_launch": ms_b * 1e3, "batched_tile": list(ptile.as_tuple()),
                    "batched_input_order_evals_per_s": npos * NSPL / (ms_bi * 1e-3),
-                   "max_norm_err": max(errs.values()), "err_per_component": errs}
+                   "max_norm_err_vs_f32_table": max(errs.values()),
+                   "err_vs_f32_table_per_component": errs}
         if dt != "f32":
             B.spline_table_destroy(t)
     for dt in ("f16", "bf16"):
@@ -292,8 +300,8 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
     out["npos"] = npos
     out["workload"] = ("eval_vgh on the same 48^3 x N=2048 coefficients stored as FP32, FP16 "
                        "and BF16 (per-spline FP32 scales), 4096 uniform positions per batch, "
-                       "4 batches cycled; errors on 64 positions vs the FP64 oracle, "
-                       "normalised per component by max|reference|")
+                       "4 batches cycled; errors on 64 positions against the FP32-table "
+                       "outputs, normalised per component by max|reference|")
     return out
 
 
