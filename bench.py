@@ -102,6 +102,9 @@ def main(argv=None):
                     help="profiling: fixed tile vw,wx,wy,grid,order instead of autotuning")
     ap.add_argument("--npos", type=int, default=NPOS,
                     help="profiling: positions per batch (the benchmark itself uses 512)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="throughput vs N (128..4096 at 48^3) and vs tile size at N=2048, "
+                         "one JSON line each, instead of the benchmark line")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args(argv)
@@ -122,6 +125,8 @@ def main(argv=None):
     from paper_1611_02665_amd import binding as B
 
     torch.cuda.set_device(0)
+    if args.sweep:
+        return sweep_mode(torch, B, A, synth)
     if args.copy_probe:
         gbs, ms = copy_probe(torch)
         print(json.dumps({"copy_probe_bytes": 1 << 30, "copy_ms": ms, "copy_gbs": gbs}))
@@ -408,6 +413,52 @@ def large_extra(torch, B, A, synth, warmup):
     for t in tabs.values():
         B.spline_table_destroy(t)
     return res
+
+
+def sweep_mode(torch, B, A, synth):
+    """The paper's throughput-vs-N and tile-size studies on this GPU:
+    T = npos * N / t for N = 128 ... 4096 at 48^3 (512 positions), each with
+    its autotuned tile, then T against the spline tile width at N = 2048."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    npos = NPOS
+    batches = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0), batch=b))
+               .to(dev) for b in range(NBATCH)]
+    for n in (128, 256, 512, 1024, 2048, 4096):
+        coef = synth.coef_table(*GRID, n, stream=synth.table_stream(0))
+        t = B.spline_table_create(*GRID, n, coef, "f32")
+        del coef
+        v = torch.empty(npos, n, device=dev)
+        g = torch.empty(npos, 3, n, device=dev)
+        h = torch.empty(npos, 6, n, device=dev)
+        for kind in ("vgh", "vgl", "v"):
+            tile = B.spline_autotune(t, kind, npos)
+            ms = timed(torch, lambda i: B.spline_eval(t, kind, npos, batches[i % NBATCH], v, g, h,
+                                                      n, stream=stream), 200, 20)
+            print(json.dumps({"sweep": "n_splines", "grid": list(GRID), "n_splines": n,
+                              "npos": npos, "kernel": "eval_" + kind, "us_per_launch": ms * 1e3,
+                              "evals_per_s": npos * n / (ms * 1e-3),
+                              "hbm_gbs": A.batch_bytes(kind, "f32", npos, n) / (ms * 1e-3) / 1e9,
+                              "tile": list(tile.as_tuple())}), flush=True)
+            if n == 2048 and kind == "vgh":
+                # tile-width study: splines per workgroup 64*vw*wx, one position row
+                for vw in (1, 2, 4):
+                    for wx in (1, 2, 4, 8):
+                        tl = (vw, wx, 1, 0, 0)
+                        ms = timed(torch, lambda i: B.spline_eval(t, kind, npos,
+                                                                  batches[i % NBATCH], v, g, h,
+                                                                  n, tile=tl, stream=stream),
+                                   200, 20)
+                        print(json.dumps({"sweep": "tile", "n_splines": n, "npos": npos,
+                                          "kernel": "eval_vgh", "tile": list(tl),
+                                          "splines_per_wavefront": 64 * vw,
+                                          "splines_per_workgroup": 64 * vw * wx,
+                                          "us_per_launch": ms * 1e3,
+                                          "evals_per_s": npos * n / (ms * 1e-3)}), flush=True)
+        B.spline_table_destroy(t)
+        del v, g, h
+        torch.cuda.empty_cache()
+    return 0
 
 
 def cpu_baseline(np, synth, coef, budget_cpu_s=12.0, max_batches=64):
