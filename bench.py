@@ -213,6 +213,28 @@ def main(argv=None):
         extra["vgl"] = {"evals_per_s": evals / (ms_l * 1e-3), "us_per_launch": ms_l * 1e3,
                         "hbm_gbs": A.batch_bytes("vgl", "f32", NPOS, NSPL) / (ms_l * 1e-3) / 1e9,
                         "tile": list(tile_l.as_tuple())}
+        # fused determinant ratios on the same workload: 64*4 table bytes +
+        # 4 bytes of inverse-matrix row per eval, no N-wide output rows
+        ainv = torch.randn(NPOS, NSPL, device=dev)
+        rout = torch.empty(NPOS, 10, dtype=torch.float64, device=dev)
+        for kind, nc in (("vgh", 10), ("vgl", 5)):
+            best = None
+            for rt in [(vw, wx, 1, 0, 0) for vw in (1, 2, 4) for wx in (2, 4, 8)]:
+                ms_r = timed(torch, lambda i: B.spline_eval_ratio(
+                    t32, kind, NPOS, pp[i % nbatch], ainv, NSPL, rout, tile=rt, stream=stream),
+                    50, 5)
+                if best is None or ms_r < best[1]:
+                    best = (rt, ms_r)
+            rt = best[0]
+            ms_r = timed(torch, lambda i: B.spline_eval_ratio(t32, kind, NPOS, pp[i % nbatch],
+                                                              ainv, NSPL, rout, tile=rt,
+                                                              stream=stream),
+                         max(100, steps // 2), warmup)
+            rb = NPOS * NSPL * (64 * 4 + 4) + NPOS * (24 + 8 * nc)
+            extra[f"ratio_{kind}"] = {"evals_per_s": evals / (ms_r * 1e-3),
+                                      "us_per_launch": ms_r * 1e3, "tile": list(rt),
+                                      "alg_bytes_per_launch": rb,
+                                      "hbm_gbs": rb / (ms_r * 1e-3) / 1e9}
         copy_gbs, _ = copy_probe(torch)
         extra["copy_gbs_measured"] = copy_gbs
         line["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs

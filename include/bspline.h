@@ -165,6 +165,25 @@ bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos,
                         const double* pos, float* v, float* g, float* lh,
                         int64_t ldo, const bspl_tile* tile, void* stream);
 
+/* Determinant ratios fused with the evaluation (paper, section "QMC and
+ * B-spline-based SPOs": after a move of electron e the determinant ratio is
+ * the sum over orbitals n of phi_n(r_e) times the inverse-matrix entry
+ * linking orbital n and electron e, and the gradient ratio is the same sum
+ * over grad phi_n).  For each position p:
+ *     out[p*ncomp + c] = sum_{n<N} X_{c,n}(r_p) * ainv[p*ld_ainv + n]
+ * with X the kind's components in the order of spline_eval (V: phi; VGL:
+ * phi, gx, gy, gz, Laplacian; VGH: phi, gx, gy, gz, hxx, hxy, hxz, hyy, hyz,
+ * hzz), ncomp = 1, 5 or 10.  ainv: device FP32 [npos][ld_ainv], row p being
+ * the N inverse-matrix entries of the electron that position p moves (for
+ * A[n][e] = phi_n(r_e), the entries (A^-1)[e][n], n = 0..N-1); ld_ainv >= N.
+ * out: device FP64 [npos][ncomp], overwritten.  The N-wide output rows are
+ * never materialised.  Products are formed in FP32 and summed in FP64 in a
+ * fixed order (the result is deterministic).  tile: vw and wx (wavefronts
+ * per position, at most 8) are used, NULL picks them.  Errors as spline_eval. */
+bspl_status spline_eval_ratio(const bspl_table* t, bspl_kind kind, int64_t npos,
+                              const double* pos, const float* ainv, int64_t ld_ainv,
+                              double* out, const bspl_tile* tile, void* stream);
+
 /* The decomposition spline_eval uses when given tile = NULL: the tuned one
  * from the wisdom cache if it holds this shape, else a built-in default.   */
 bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos,

@@ -56,6 +56,10 @@ def _bind(path: str):
                                            ctypes.c_int64, dp, dp, ctypes.c_int64, dp,
                                            dp, dp, dp, dp, ctypes.c_int64]
     lib.oracle_eval_bruteforce.restype = ctypes.c_int
+    lib.oracle_eval_ratio.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, dp,
+                                      ctypes.c_int64, dp, dp, ctypes.c_int64, dp]
+    lib.oracle_eval_ratio.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     return lib
 
@@ -86,6 +90,9 @@ class Oracle:
 
     def evaluate_bruteforce(self, coef, pos, box=(1.0, 1.0, 1.0)):
         return evaluate_bruteforce(coef, pos, box, _lib_=self._l())
+
+    def evaluate_ratio(self, kind, coef, pos, ainv, box=(1.0, 1.0, 1.0)):
+        return evaluate_ratio(kind, coef, pos, ainv, box, _lib_=self._l())
 
 
 def _dp(a):
@@ -186,3 +193,30 @@ def evaluate_bruteforce(coef: np.ndarray, pos: np.ndarray, box=(1.0, 1.0, 1.0),
     if rc != 0:
         raise ValueError("oracle_eval_bruteforce rejected its arguments")
     return {"v": v, "g": g, "l": l, "h": h}
+
+
+def evaluate_ratio(kind, coef: np.ndarray, pos: np.ndarray, ainv: np.ndarray,
+                   box=(1.0, 1.0, 1.0), _lib_=None) -> np.ndarray:
+    """Determinant ratios ``[npos][ncomp]``: sum_n X_{c,n}(r_p) * ainv[p][n]."""
+    kind = KINDS.get(kind, kind)
+    lib = _lib_ or _load()
+    coef = np.ascontiguousarray(coef)
+    if coef.dtype == np.float32:
+        cdt = 1
+    else:
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        cdt = 0
+    nx, ny, nz, ncoef = coef.shape
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    npos = pos.shape[1]
+    ainv = np.ascontiguousarray(ainv, dtype=np.float64)
+    if ainv.shape[0] != npos or ainv.shape[1] < ncoef:
+        raise ValueError("ainv must be [npos][>= N]")
+    ncomp = {V: 1, VGL: 5, VGH: 10}[kind]
+    out = np.empty((npos, ncomp))
+    bx = np.asarray(box, dtype=np.float64)
+    rc = lib.oracle_eval_ratio(kind, nx, ny, nz, ncoef, coef.ctypes.data_as(ctypes.c_void_p), cdt,
+                               _dp(bx), npos, _dp(pos), _dp(ainv), ainv.shape[1], _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_eval_ratio rejected its arguments")
+    return out

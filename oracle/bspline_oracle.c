@@ -195,6 +195,48 @@ int oracle_eval(int kind, int nx, int ny, int nz, int64_t ncoef,
     return status;
 }
 
+int oracle_eval_ratio(int kind, int nx, int ny, int nz, int64_t ncoef,
+                      const void* coef, int coef_dtype, const double box[3],
+                      int64_t npos, const double* pos, const double* ainv,
+                      int64_t ld_ainv, double* out)
+{
+    if (kind < ORACLE_V || kind > ORACLE_VGH || npos < 0 || ncoef <= 0 || ld_ainv < ncoef ||
+        (npos > 0 && (!pos || !ainv || !out)))
+        return -1;
+    const int ncomp = kind == ORACLE_V ? 1 : (kind == ORACLE_VGL ? 5 : 10);
+    if (npos == 0) return 0;
+    /* first the orbitals and their derivatives (Eq. TricubicValue) ... */
+    double* v = (double*)malloc(sizeof(double) * (size_t)(npos * ncoef));
+    double* g = kind >= ORACLE_VGL ? (double*)malloc(sizeof(double) * (size_t)(npos * 3 * ncoef)) : NULL;
+    double* l = kind == ORACLE_VGL ? (double*)malloc(sizeof(double) * (size_t)(npos * ncoef)) : NULL;
+    double* h = kind == ORACLE_VGH ? (double*)malloc(sizeof(double) * (size_t)(npos * 6 * ncoef)) : NULL;
+    int rc = -1;
+    if (v && (kind < ORACLE_VGL || g) && (kind != ORACLE_VGL || l) && (kind != ORACLE_VGH || h))
+        rc = oracle_eval(kind, nx, ny, nz, ncoef, coef, coef_dtype, 0, box, npos, pos, v, g, l,
+                         h, ncoef);
+    /* ... then the ratio sums over the orbitals */
+    if (rc == 0) {
+        for (int64_t p = 0; p < npos; ++p) {
+            const double* a = ainv + p * ld_ainv;
+            for (int c = 0; c < ncomp; ++c) {
+                const double* x;
+                if (c == 0) x = v + p * ncoef;
+                else if (c <= 3) x = g + (p * 3 + (c - 1)) * ncoef;
+                else if (kind == ORACLE_VGL) x = l + p * ncoef;
+                else x = h + (p * 6 + (c - 4)) * ncoef;
+                double sum = 0.0;
+                for (int64_t n = 0; n < ncoef; ++n) sum += x[n] * a[n];
+                out[p * ncomp + c] = sum;
+            }
+        }
+    }
+    free(v);
+    free(g);
+    free(l);
+    free(h);
+    return rc;
+}
+
 /* Periodic sum of the basis over images: S(u, m) = sum_k B(u - m - k n). */
 static void image_sum(double u, int m, int n, double delta, double* s, double* ds, double* d2s)
 {

@@ -63,6 +63,19 @@ int oracle_eval_bruteforce(int nx, int ny, int nz, int64_t ncoef,
                            int64_t npos, const double* pos,
                            double* v, double* g, double* l, double* h, int64_t ldo);
 
+/* Determinant ratios (paper, "QMC and B-spline-based SPOs": the ratio of
+ * determinants after a one-electron move and its gradient are sums over the
+ * orbitals of phi_n(r_e), resp. grad phi_n(r_e), times the inverse-matrix
+ * entry of (n, e)).  For each position p and output component c of `kind`
+ * (same components and order as oracle_eval: V -> v; VGL -> v, gx, gy, gz,
+ * l; VGH -> v, gx, gy, gz, hxx, hxy, hxz, hyy, hyz, hzz):
+ *   out[p*ncomp + c] = sum_n X_{c,n}(r_p) * ainv[p*ld_ainv + n]
+ * ainv is FP64 [npos][ld_ainv].  Returns 0, or -1 as oracle_eval.         */
+int oracle_eval_ratio(int kind, int nx, int ny, int nz, int64_t ncoef,
+                      const void* coef, int coef_dtype, const double box[3],
+                      int64_t npos, const double* pos, const double* ainv,
+                      int64_t ld_ainv, double* out);
+
 /* Number of OpenMP threads an oracle_eval call uses. */
 int oracle_num_threads(void);
 

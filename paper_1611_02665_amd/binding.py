@@ -79,6 +79,7 @@ _SIGS = {
     "spline_eval_vgl": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp]),
     "spline_eval_vgh": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp]),
     "spline_eval": (_int, [_vp, _int, _i64, _vp, _vp, _vp, _vp, _i64, _P(bspl_tile), _vp]),
+    "spline_eval_ratio": (_int, [_vp, _int, _i64, _vp, _vp, _i64, _vp, _P(bspl_tile), _vp]),
     "spline_tile_select": (_int, [_vp, _int, _i64, _P(bspl_tile)]),
     "spline_autotune": (_int, [_vp, _int, _i64, ctypes.c_char_p, _P(bspl_tile), _vp]),
     "spline_wisdom_load": (_int, [ctypes.c_char_p]),
@@ -202,6 +203,11 @@ def spline_eval(table, kind, npos, pos, v, g=None, lh=None, ldo=None, tile=None,
                 stream=None) -> None:
     _check(lib.spline_eval(table, _enum(kind, KINDS), npos, _ptr(pos), _ptr(v), _ptr(g),
                            _ptr(lh), ldo, _tile(tile), _stream(stream)), "spline_eval")
+
+
+def spline_eval_ratio(table, kind, npos, pos, ainv, ld_ainv, out, tile=None, stream=None) -> None:
+    _check(lib.spline_eval_ratio(table, _enum(kind, KINDS), npos, _ptr(pos), _ptr(ainv), ld_ainv,
+                                 _ptr(out), _tile(tile), _stream(stream)), "spline_eval_ratio")
 
 
 def spline_tile_select(table, kind, npos) -> bspl_tile:

@@ -174,8 +174,13 @@ template <typename T, int VW> struct Depth {
     static constexpr int value = 32 / (VW * Elem<T>::bytes) < 2 ? 2 : 32 / (VW * Elem<T>::bytes);
 };
 
+// Steps 1-3 (and the scale of step 4) for one work unit: on return acc holds
+// the unit's outputs for splines [n0, n0 + VW) of lane `lane`, of which
+// `valid` (if positive) are real splines.
 template <typename T, int VW, int KIND, int DEPTH = Depth<T, VW>::value>
-__device__ __forceinline__ void eval_unit(const TableDesc& d, int p, int chunk, int lane) {
+__device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, int lane,
+                                          float (&acc)[Shape<KIND>::nout][VW], int& n0_out,
+                                          int& valid_out) {
     constexpr int EB = Elem<T>::bytes;
     constexpr int NOUT = Shape<KIND>::nout;
     constexpr int NY = Shape<KIND>::ny;
@@ -245,7 +250,6 @@ __device__ __forceinline__ void eval_unit(const TableDesc& d, int p, int chunk, 
         for (int k = 0; k < 4; ++k) ring[slot][k] = RowT::load(base + (go + (uint32_t)k * d.row_bytes));
     };
 
-    float acc[NOUT][VW];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o)
 #pragma unroll
@@ -335,7 +339,9 @@ __device__ __forceinline__ void eval_unit(const TableDesc& d, int p, int chunk, 
         }
     }
 
-    // 4. scale (reduced-precision tables) and write
+    // 4a. per-spline scale of reduced-precision tables
+    n0_out = n0;
+    valid_out = valid;
     if (valid <= 0) return;
     if constexpr (Elem<T>::bytes == 2) {
         float sc[VW];
@@ -346,6 +352,15 @@ __device__ __forceinline__ void eval_unit(const TableDesc& d, int p, int chunk, 
 #pragma unroll
             for (int e = 0; e < VW; ++e) acc[o][e] *= sc[e];
     }
+}
+
+// One work unit: evaluate, then 4b. write the 1, 5 or 10 SoA output rows.
+template <typename T, int VW, int KIND>
+__device__ __forceinline__ void eval_unit(const TableDesc& d, int p, int chunk, int lane) {
+    float acc[Shape<KIND>::nout][VW];
+    int n0, valid;
+    eval_core<T, VW, KIND>(d, p, chunk, lane, acc, n0, valid);
+    if (valid <= 0) return;
     const bool vec = d.vec_store != 0;
     const int64_t ldo = d.ldo;
     store_row<VW>(d.v + (int64_t)p * ldo + n0, acc[0], valid, vec);
@@ -400,6 +415,101 @@ __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
             eval_unit<T, VW, KIND>(d, p, chunk, lane);
         }
     }
+}
+
+// Determinant-ratio consumer fused into the evaluation (paper: the ratio of
+// determinants after a one-electron move is the sum over orbitals of
+// phi_n(r_e) times the inverse-matrix entry of (n, e), and its gradient the
+// same sum over grad phi_n; "QMC and B-spline-based SPOs").  For position p:
+//   out[p][c] = sum_n X_c,n(r_p) * ainv[p][n]
+// for every output component X_c of the kind (phi; grad phi; Laplacian or
+// Hessian).  One workgroup of W wavefronts owns one position; wavefront w
+// reduces spline tiles w, w+W, ...; per-lane FP32 products are summed in FP64,
+// reduced across the wavefront with shuffles and across the workgroup in LDS,
+// in a fixed order, so the result is deterministic.  The N output rows are
+// never written: a position reads its N-entry ainv row instead.
+template <typename T, int VW, int KIND>
+__global__ void __launch_bounds__(512) ratio_kernel(const TableDesc d, const float* ainv,
+                                                    int64_t ld_ainv, double* out) {
+    constexpr int NOUT = Shape<KIND>::nout;
+    __shared__ double red[8][NOUT];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int W = (int)(blockDim.x >> 6);
+    for (int64_t pb = blockIdx.x; pb < d.npos; pb += gridDim.x) {
+        const int p = (int)pb;
+        double part[NOUT];
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) part[o] = 0.0;
+        for (int c = wave; c < d.nchunks; c += W) {
+            float acc[NOUT][VW];
+            int n0, valid;
+            eval_core<T, VW, KIND>(d, p, c, lane, acc, n0, valid);
+            if (valid > 0) {
+                float a[VW];
+                const float* row = ainv + (int64_t)p * ld_ainv + n0;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) a[e] = e < valid ? row[e] : 0.f;
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o) {
+                    float sum = 0.f;
+#pragma unroll
+                    for (int e = 0; e < VW; ++e)
+                        if (e < valid) sum = fmaf(acc[o][e], a[e], sum);
+                    part[o] += (double)sum;
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) part[o] += __shfl_xor(part[o], off, 64);
+        if (lane == 0)
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o) red[wave][o] = part[o];
+        __syncthreads();
+        if (wave == 0 && lane < NOUT) {
+            double sum = 0.0;
+            for (int w = 0; w < W; ++w) sum += red[w][lane];
+            out[(int64_t)p * NOUT + lane] = sum;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int KIND>
+const void* pick_ratio(int vw) {
+    if constexpr (Elem<T>::bytes == 4) {
+        switch (vw) {
+        case 1: return (const void*)&ratio_kernel<T, 1, KIND>;
+        case 2: return (const void*)&ratio_kernel<T, 2, KIND>;
+        case 4: return (const void*)&ratio_kernel<T, 4, KIND>;
+        }
+    } else {
+        switch (vw) {
+        case 2: return (const void*)&ratio_kernel<T, 2, KIND>;
+        case 4: return (const void*)&ratio_kernel<T, 4, KIND>;
+        case 8: return (const void*)&ratio_kernel<T, 8, KIND>;
+        }
+    }
+    return nullptr;
+}
+
+const void* ratio_kernel_for(int dtype, int kind, int vw) {
+#define BSPL_RKINDS(T)                                        \
+    switch (kind) {                                           \
+    case BSPL_V: return pick_ratio<T, BSPL_V>(vw);            \
+    case BSPL_VGL: return pick_ratio<T, BSPL_VGL>(vw);        \
+    case BSPL_VGH: return pick_ratio<T, BSPL_VGH>(vw);        \
+    }                                                         \
+    return nullptr;
+    switch (dtype) {
+    case BSPL_F32: { BSPL_RKINDS(F32) }
+    case BSPL_F16: { BSPL_RKINDS(F16) }
+    case BSPL_BF16: { BSPL_RKINDS(BF16) }
+    }
+#undef BSPL_RKINDS
+    return nullptr;
 }
 
 template <typename T, int KIND, int MAXT>
@@ -474,6 +584,21 @@ bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
 
 const void* multi_kernel_ptr(int dtype, int kind, int vw) {
     return kernel_for<kMaxTables>(dtype, kind, vw);
+}
+
+bspl_status launch_ratio(const bspl_table* t, int kind, const TableDesc& d, const float* ainv,
+                         int64_t ld_ainv, double* out, const bspl_tile& tile, hipStream_t s) {
+    const void* fn = ratio_kernel_for(t->info.dtype, kind, tile.vw);
+    if (!fn) return fail(BSPL_EINVAL, "no ratio kernel for this dtype/kind/vw");
+    if (d.npos <= 0) return BSPL_OK;
+    int waves = tile.wx < d.nchunks ? tile.wx : d.nchunks;
+    if (waves < 1) waves = 1;
+    int64_t grid = d.npos;
+    if (tile.grid > 0 && tile.grid < grid) grid = tile.grid;
+    TableDesc dd = d;
+    void* args[] = {&dd, const_cast<float**>(&ainv), &ld_ainv, &out};
+    BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64 * waves), args, 0, s));
+    return BSPL_OK;
 }
 
 }  // namespace bspl

@@ -84,6 +84,8 @@ bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
                           const bspl_tile& tile, hipStream_t s);
 bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
                          const bspl_tile& tile, hipStream_t s);
+bspl_status launch_ratio(const bspl_table* t, int kind, const TableDesc& d, const float* ainv,
+                         int64_t ld_ainv, double* out, const bspl_tile& tile, hipStream_t s);
 // Address of the batched kernel for a configuration (graph node building).
 const void* multi_kernel_ptr(int dtype, int kind, int vw);
 

@@ -289,6 +289,35 @@ bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const
     return st;
 }
 
+bspl_status spline_eval_ratio(const bspl_table* t, bspl_kind kind, int64_t npos,
+                              const double* pos, const float* ainv, int64_t ld_ainv, double* out,
+                              const bspl_tile* tile, void* stream) {
+    if (!t) return fail(BSPL_EINVAL, "table is NULL");
+    if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
+    if (npos < 0) return fail(BSPL_EINVAL, "npos %lld < 0", (long long)npos);
+    if (ld_ainv < t->info.n_splines)
+        return fail(BSPL_EINVAL, "ld_ainv %lld < n_splines %lld", (long long)ld_ainv,
+                    (long long)t->info.n_splines);
+    if (npos == 0) return BSPL_OK;
+    if (npos > INT32_MAX) return fail(BSPL_EUNSUPPORTED, "npos beyond 2^31-1");
+    if (!pos || !ainv || !out) return fail(BSPL_EINVAL, "pos, ainv or out is NULL");
+    bspl_tile tl;
+    if (tile) {
+        tl = *tile;
+        if (!tile_valid(tl, t->info.dtype))
+            return fail(BSPL_EINVAL, "tile invalid for dtype %d", t->info.dtype);
+    } else {
+        tl = default_tile(t, kind, npos);
+        const int64_t chunks = (t->info.n_splines + 64 * tl.vw - 1) / (64 * tl.vw);
+        tl.wx = (int)std::min<int64_t>(8, chunks);
+    }
+    TableDesc d;
+    bspl_status st = make_desc(t, npos, pos, nullptr, nullptr, nullptr, t->info.n_splines, tl.vw,
+                               1, 1, &d);
+    if (st != BSPL_OK) return st;
+    return launch_ratio(t, kind, d, ainv, ld_ainv, out, tl, static_cast<hipStream_t>(stream));
+}
+
 bspl_status spline_eval_v(const bspl_table* t, int64_t npos, const double* pos, float* v,
                           int64_t ldo, void* stream) {
     return spline_eval(t, BSPL_V, npos, pos, v, nullptr, nullptr, ldo, nullptr, stream);

@@ -278,7 +278,7 @@ def orc():
     return oracle.Oracle()
 
 
-@pytest.mark.parametrize("check", ALL_CHECKS, ids=[c.__name__ for c in ALL_CHECKS])
+@pytest.mark.parametrize("check", list(ALL_CHECKS), ids=[c.__name__ for c in ALL_CHECKS])
 def test_oracle_pin(orc, check):
     check(orc)
 
@@ -354,3 +354,71 @@ def test_planted_mistakes_fail_a_pin():
             if caught is None:
                 survivors.append(pat)
         assert not survivors, f"planted mistakes no pin caught: {survivors}"
+
+
+# ---------------------------------------------------------- determinant ratios
+def _bf_matrix(orc, coef, pos, box):
+    """A[n][e] = phi_n(r_e) and derivatives from the brute-force evaluator."""
+    return orc.evaluate_bruteforce(coef, pos, box=box)
+
+
+def check_ratio_is_determinant_ratio(orc):
+    """The ratio sum equals det(A')/det(A) for A[n][e] = phi_n(r_e), A' with
+    column e replaced by phi(r'), ainv row = (A^-1)[e, :]; its gradient,
+    Laplacian and Hessian match finite differences of that determinant
+    ratio (all built from the brute-force evaluator)."""
+    rng = np.random.default_rng(11)
+    dims, nel = (4, 3, 5), 6
+    box = (1.0, 0.9, 1.2)
+    coef = rng.uniform(-1, 1, dims + (nel,))
+    r = rng.random((3, nel)) * np.array(box)[:, None]
+    A = _bf_matrix(orc, coef, r, box)["v"].T            # A[n][e]
+    Ainv = np.linalg.inv(A)
+    detA = np.linalg.det(A)
+    e = 2
+    rnew = (rng.random(3) * np.array(box))[:, None]
+
+    def R(x):
+        phi = _bf_matrix(orc, coef, x[:, None], box)["v"][0]
+        A2 = A.copy()
+        A2[:, e] = phi
+        return np.linalg.det(A2) / detA
+
+    got = orc.evaluate_ratio("vgh", coef, rnew, Ainv[e][None, :], box=box)[0]
+    gotl = orc.evaluate_ratio("vgl", coef, rnew, Ainv[e][None, :], box=box)[0]
+    gotv = orc.evaluate_ratio("v", coef, rnew, Ainv[e][None, :], box=box)[0]
+    x0 = rnew[:, 0]
+    assert abs(got[0] - R(x0)) < 1e-10 * max(1, abs(R(x0)))
+    assert abs(gotv[0] - got[0]) < 1e-14 and abs(gotl[0] - got[0]) < 1e-14
+    hstep = 1e-4 * min(b / n for b, n in zip(box, dims))
+    grad = np.zeros(3)
+    hess = np.zeros((3, 3))
+    for a in range(3):
+        da = np.zeros(3)
+        da[a] = hstep
+        grad[a] = (R(x0 + da) - R(x0 - da)) / (2 * hstep)
+        for b in range(3):
+            db = np.zeros(3)
+            db[b] = hstep
+            hess[a, b] = (R(x0 + da + db) - R(x0 + da - db) - R(x0 - da + db)
+                          + R(x0 - da - db)) / (4 * hstep * hstep)
+    scale_g = np.abs(grad).max()
+    np.testing.assert_allclose(got[1:4], grad, atol=1e-5 * scale_g)
+    np.testing.assert_allclose(gotl[1:4], grad, atol=1e-5 * scale_g)
+    hidx = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    scale_h = np.abs(hess).max()
+    np.testing.assert_allclose(got[4:], [hess[i, j] for i, j in hidx], atol=1e-4 * scale_h)
+    assert abs(gotl[4] - np.trace(hess)) < 1e-4 * scale_h
+
+
+def test_ratio_pin(orc):
+    check_ratio_is_determinant_ratio(orc)
+
+
+ALL_CHECKS.append(check_ratio_is_determinant_ratio)
+MUTANTS += [
+    ("else if (c <= 3) x = g + (p * 3 + (c - 1)) * ncoef;",
+     "else if (c <= 3) x = g + (p * 3 + (3 - c)) * ncoef;"),  # gradient components reversed
+    ("for (int64_t n = 0; n < ncoef; ++n) sum += x[n] * a[n];",
+     "for (int64_t n = 0; n < ncoef; ++n) sum += x[n] * a[ncoef - 1 - n];"),  # ainv reversed
+]

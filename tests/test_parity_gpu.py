@@ -362,3 +362,83 @@ def test_two_streams_share_a_table(cfg1):
         b, _ = run_gpu(B, t.h, "vgh", p2, 64, stream=s2)
     assert_close("vgh", a, oracle.evaluate("vgh", coef, p1))
     assert_close("vgh", b, oracle.evaluate("vgh", coef, p2))
+
+
+# -------------------------------------------- fused determinant ratios
+def _ratio_errors(gpu, ref, scale):
+    return np.abs(gpu - ref).max(axis=0) / scale
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("kind", ["v", "vgl", "vgh"])
+def test_ratio_matches_oracle(kind, dtype):
+    """spline_eval_ratio against the oracle's ratio sums, each component
+    normalised by max_p sum_n |X_n(r_p) ainv[p][n]| (the size of its terms)."""
+    coef = synth.coef_table(11, 9, 13, 700, stream=15)   # N ragged for every vw
+    box = (1.1, 0.9, 1.3)
+    npos = 200
+    pos = (synth.positions(npos, stream=16) * 3 - 1) * np.array(box)[:, None]
+    rng = np.random.default_rng(17)
+    ld = 710
+    ainv = rng.standard_normal((npos, ld)).astype(np.float32)
+    deq = dequantized(coef, dtype).astype(np.float64)
+    ref = oracle.evaluate_ratio(kind, deq, pos, ainv[:, :700].astype(np.float64), box=box)
+    full = oracle.evaluate(kind, deq, pos, box=box)
+    comps = [full["v"]]
+    if kind != "v":
+        comps += [full["g"][:, c] for c in range(3)]
+    if kind == "vgl":
+        comps.append(full["l"])
+    if kind == "vgh":
+        comps += [full["h"][:, c] for c in range(6)]
+    scale = np.array([np.abs(x * ainv[:, :700]).sum(axis=1).max() for x in comps])
+    dev = torch.device("cuda")
+    with Table(coef, dtype, box) as t:
+        pd = torch.from_numpy(pos).to(dev)
+        ad = torch.from_numpy(ainv).to(dev)
+        for tile in (None, (1 if dtype == "f32" else 2, 3, 1, 0, 0), (4, 8, 1, 17, 0)):
+            out = torch.full((npos, ref.shape[1]), 7.0, dtype=torch.float64, device=dev)
+            B.spline_eval_ratio(t.h, kind, npos, pd, ad, ld, out, tile=tile)
+            torch.cuda.synchronize()
+            err = _ratio_errors(out.cpu().numpy(), ref, scale)
+            assert np.all(err <= 1e-5), (tile, err)
+        # deterministic: the same call twice gives the same bits
+        o1 = torch.empty((npos, ref.shape[1]), dtype=torch.float64, device=dev)
+        o2 = torch.empty_like(o1)
+        B.spline_eval_ratio(t.h, kind, npos, pd, ad, ld, o1)
+        B.spline_eval_ratio(t.h, kind, npos, pd, ad, ld, o2)
+        torch.cuda.synchronize()
+        assert torch.equal(o1, o2)
+
+
+def test_ratio_equals_contracted_outputs(cfg1):
+    """Fused ratio = host contraction of the unfused GPU outputs with ainv."""
+    coef, pos, t = cfg1
+    rng = np.random.default_rng(18)
+    ainv = rng.standard_normal((1024, 64)).astype(np.float32)
+    dev = torch.device("cuda")
+    out = torch.empty((1024, 10), dtype=torch.float64, device=dev)
+    B.spline_eval_ratio(t.h, "vgh", 1024, torch.from_numpy(pos).to(dev),
+                        torch.from_numpy(ainv).to(dev), 64, out)
+    gpu, _ = run_gpu(B, t.h, "vgh", pos, 64)
+    torch.cuda.synchronize()
+    a = ainv.astype(np.float64)
+    host = np.stack([(gpu["v"] * a).sum(1)] + [(gpu["g"][:, c] * a).sum(1) for c in range(3)]
+                    + [(gpu["h"][:, c] * a).sum(1) for c in range(6)], axis=1)
+    scale = np.abs(host).max(axis=0) + 1e-30
+    assert np.all(np.abs(out.cpu().numpy() - host).max(axis=0) / scale <= 1e-5)
+
+
+def test_ratio_argument_errors(cfg1):
+    _, pos, t = cfg1
+    dev = torch.device("cuda")
+    out = torch.empty((4, 1), dtype=torch.float64, device=dev)
+    a = torch.zeros((4, 64), device=dev)
+    p = torch.from_numpy(pos[:, :4].copy()).to(dev)
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_eval_ratio(t.h, "v", 4, p, a, 63, out)
+    assert e.value.status == B.BSPL_EINVAL
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_eval_ratio(t.h, "v", 4, p, None, 64, out)
+    assert e.value.status == B.BSPL_EINVAL
+    B.spline_eval_ratio(t.h, "v", 0, None, None, 64, None)
