@@ -81,7 +81,8 @@ typedef struct {
     int32_t elem_bytes;       /* 4 or 2 */
     int64_t row_bytes;        /* n_padded * elem_bytes */
     int64_t table_bytes;      /* px*py*pz*row_bytes */
-    double box[3];            /* orthorhombic box lengths */
+    double box[3];            /* cell vector lengths (the box of an orthorhombic cell) */
+    double lattice[9];        /* cell vectors a1, a2, a3 as rows (Cartesian) */
     const void* data;         /* device pointer to the table (read-only) */
     const float* scales;      /* device pointer to n_padded scales, or NULL */
 } bspl_table_info;
@@ -136,6 +137,22 @@ bspl_status spline_table_create(bspl_table** out, int nx, int ny, int nz,
                                 int64_t n_splines, const float* coefs,
                                 bspl_dtype dtype, const double box[3],
                                 unsigned flags, void* stream);
+
+/* Create a table on a general (triclinic, e.g. hexagonal) periodic cell.
+ *  lattice: the cell vectors a1, a2, a3 (Cartesian, rows of a 3x3 matrix,
+ *  row-major).  Grid point (i, j, k) sits at (i/nx) a1 + (j/ny) a2 + (k/nz) a3;
+ *  a position r has grid coordinates u = (nx s1, ny s2, nz s3) with
+ *  s = r A^-1 its fractional coordinates, and wraps periodically in each of
+ *  them.  Gradients and Hessians are Cartesian (grad_r = M^T grad_u,
+ *  H_r = M^T H_u M with M = d u / d r), and the Laplacian is trace H_r.
+ *  This is an extension beyond the paper's orthorhombic grids, needed for
+ *  real orbitals on non-orthogonal cells.  A diagonal lattice is exactly
+ *  spline_table_create with box = the diagonal.  Errors as
+ *  spline_table_create; EINVAL also for a singular or non-finite lattice.  */
+bspl_status spline_table_create_lattice(bspl_table** out, int nx, int ny, int nz,
+                                        int64_t n_splines, const float* coefs,
+                                        bspl_dtype dtype, const double lattice[9],
+                                        unsigned flags, void* stream);
 
 /* Free a table.  NULL is accepted.  No evaluation may still be in flight on
  * it (hipFree semantics). */

@@ -60,6 +60,11 @@ def _bind(path: str):
                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, dp,
                                       ctypes.c_int64, dp, dp, ctypes.c_int64, dp]
     lib.oracle_eval_ratio.restype = ctypes.c_int
+    lib.oracle_eval_lattice.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                                        ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp, dp, dp,
+                                        ctypes.c_int64]
+    lib.oracle_eval_lattice.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     return lib
 
@@ -93,6 +98,9 @@ class Oracle:
 
     def evaluate_ratio(self, kind, coef, pos, ainv, box=(1.0, 1.0, 1.0)):
         return evaluate_ratio(kind, coef, pos, ainv, box, _lib_=self._l())
+
+    def evaluate_lattice(self, kind, coef, pos, lattice, padded=False):
+        return evaluate_lattice(kind, coef, pos, lattice, padded, _lib_=self._l())
 
 
 def _dp(a):
@@ -219,4 +227,37 @@ def evaluate_ratio(kind, coef: np.ndarray, pos: np.ndarray, ainv: np.ndarray,
                                _dp(bx), npos, _dp(pos), _dp(ainv), ainv.shape[1], _dp(out))
     if rc != 0:
         raise ValueError("oracle_eval_ratio rejected its arguments")
+    return out
+
+
+def evaluate_lattice(kind, coef: np.ndarray, pos: np.ndarray, lattice, padded: bool = False,
+                     _lib_=None) -> dict:
+    """V / VGL / VGH on a general cell; ``lattice`` rows are the cell vectors."""
+    kind = KINDS.get(kind, kind)
+    lib = _lib_ or _load()
+    coef = np.ascontiguousarray(coef)
+    if coef.dtype == np.float32:
+        cdt = 1
+    else:
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        cdt = 0
+    nx, ny, nz, ncoef = coef.shape
+    if padded:
+        nx, ny, nz = nx - 3, ny - 3, nz - 3
+    pos = np.ascontiguousarray(pos, dtype=np.float64)
+    npos = pos.shape[1]
+    v, g, l, h = _outputs(kind, npos, ncoef)
+    lat = np.ascontiguousarray(np.asarray(lattice, dtype=np.float64).reshape(9))
+    rc = lib.oracle_eval_lattice(kind, nx, ny, nz, ncoef, coef.ctypes.data_as(ctypes.c_void_p),
+                                 cdt, 1 if padded else 0, _dp(lat), npos, _dp(pos), _dp(v),
+                                 _dp(g), _dp(l), _dp(h), ncoef)
+    if rc != 0:
+        raise ValueError("oracle_eval_lattice rejected its arguments")
+    out = {"v": v}
+    if g is not None:
+        out["g"] = g
+    if l is not None:
+        out["l"] = l
+    if h is not None:
+        out["h"] = h
     return out

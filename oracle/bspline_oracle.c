@@ -237,6 +237,112 @@ int oracle_eval_ratio(int kind, int nx, int ny, int nz, int64_t ncoef,
     return rc;
 }
 
+/* Inverse of a 3x3 matrix by Gauss-Jordan elimination with partial
+ * pivoting; returns -1 if it is singular. */
+static int invert3(const double a_in[9], double inv[9])
+{
+    double a[3][6];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 6; ++j)
+            a[i][j] = j < 3 ? a_in[3 * i + j] : (j - 3 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 3; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
+        if (!(fabs(a[piv][c]) > 0.0)) return -1;
+        for (int j = 0; j < 6; ++j) {
+            double tmp = a[c][j];
+            a[c][j] = a[piv][j];
+            a[piv][j] = tmp;
+        }
+        double d = a[c][c];
+        for (int j = 0; j < 6; ++j) a[c][j] /= d;
+        for (int r = 0; r < 3; ++r) {
+            if (r == c) continue;
+            double f = a[r][c];
+            for (int j = 0; j < 6; ++j) a[r][j] -= f * a[c][j];
+        }
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) inv[3 * i + j] = a[i][j + 3];
+    return 0;
+}
+
+int oracle_eval_lattice(int kind, int nx, int ny, int nz, int64_t ncoef,
+                        const void* coef, int coef_dtype, int padded,
+                        const double lattice[9], int64_t npos, const double* pos,
+                        double* v, double* g, double* l, double* h, int64_t ldo)
+{
+    if (!lattice || kind < ORACLE_V || kind > ORACLE_VGH || npos < 0 || ncoef <= 0 ||
+        ldo < ncoef || (npos > 0 && (!pos || !v)))
+        return -1;
+    if (kind >= ORACLE_VGL && npos > 0 && !g) return -1;
+    if (kind == ORACLE_VGL && npos > 0 && !l) return -1;
+    if (kind == ORACLE_VGH && npos > 0 && !h) return -1;
+    double ainv[9];
+    if (invert3(lattice, ainv) != 0) return -1;
+    const int dims[3] = {nx, ny, nz};
+    /* M[d][a] = du_d/dr_a = n_d (A^-1)[a][d] */
+    double M[3][3];
+    for (int d = 0; d < 3; ++d)
+        for (int a = 0; a < 3; ++a) M[d][a] = dims[d] * ainv[3 * a + d];
+    if (npos == 0) return 0;
+    /* 1. grid coordinates of every position */
+    double* u = (double*)malloc(sizeof(double) * 3 * (size_t)npos);
+    double* gu = (double*)malloc(sizeof(double) * 3 * (size_t)(npos * ncoef));
+    double* hu = (double*)malloc(sizeof(double) * 6 * (size_t)(npos * ncoef));
+    int rc = -1;
+    if (u && gu && hu) {
+        for (int64_t p = 0; p < npos; ++p)
+            for (int d = 0; d < 3; ++d)
+                u[d * npos + p] = M[d][0] * pos[p] + M[d][1] * pos[npos + p] +
+                                  M[d][2] * pos[2 * npos + p];
+        /* 2. the spline in grid units (a box of n_d cells of unit width) */
+        const double unit_box[3] = {nx, ny, nz};
+        rc = oracle_eval(kind == ORACLE_V ? ORACLE_V : ORACLE_VGH, nx, ny, nz, ncoef, coef,
+                         coef_dtype, padded, unit_box, npos, u, v, gu, NULL, hu, ncoef);
+    }
+    /* 3. chain rule to Cartesian derivatives */
+    if (rc == 0 && kind >= ORACLE_VGL) {
+        static const int hrow[6] = {0, 0, 0, 1, 1, 2}, hcol[6] = {0, 1, 2, 1, 2, 2};
+        for (int64_t p = 0; p < npos; ++p)
+            for (int64_t n = 0; n < ncoef; ++n) {
+                double G[3], H[3][3];
+                for (int d = 0; d < 3; ++d) G[d] = gu[(p * 3 + d) * ncoef + n];
+                for (int k = 0; k < 6; ++k) {
+                    double x = hu[(p * 6 + k) * ncoef + n];
+                    H[hrow[k]][hcol[k]] = x;
+                    H[hcol[k]][hrow[k]] = x;
+                }
+                for (int a = 0; a < 3; ++a) {
+                    double s = 0.0;
+                    for (int d = 0; d < 3; ++d) s += M[d][a] * G[d];
+                    g[(p * 3 + a) * ldo + n] = s;
+                }
+                double Hr[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        double s = 0.0;
+                        for (int d = 0; d < 3; ++d)
+                            for (int e = 0; e < 3; ++e) s += M[d][a] * M[e][b] * H[d][e];
+                        Hr[a][b] = s;
+                    }
+                if (kind == ORACLE_VGL)
+                    l[p * ldo + n] = Hr[0][0] + Hr[1][1] + Hr[2][2];
+                else
+                    for (int k = 0; k < 6; ++k) h[(p * 6 + k) * ldo + n] = Hr[hrow[k]][hcol[k]];
+            }
+    }
+    /* copy V to the caller's stride */
+    if (rc == 0 && ldo != ncoef)
+        for (int64_t p = npos - 1; p >= 0; --p)
+            for (int64_t n = ncoef - 1; n >= 0; --n) v[p * ldo + n] = v[p * ncoef + n];
+    free(u);
+    free(gu);
+    free(hu);
+    return rc;
+}
+
 /* Periodic sum of the basis over images: S(u, m) = sum_k B(u - m - k n). */
 static void image_sum(double u, int m, int n, double delta, double* s, double* ds, double* d2s)
 {

@@ -76,6 +76,16 @@ int oracle_eval_ratio(int kind, int nx, int ny, int nz, int64_t ncoef,
                       int64_t npos, const double* pos, const double* ainv,
                       int64_t ld_ainv, double* out);
 
+/* General periodic cell with vectors a_i = lattice[3i..3i+2] (rows of A).
+ * Grid coordinates u_d = n_d (r A^-1)_d; the spline is evaluated in grid
+ * units and its derivatives carried to Cartesian ones by the chain rule
+ * (M = du/dr: g_r = M^T g_u, H_r = M^T H_u M, L = trace H_r).  Arguments
+ * and outputs as oracle_eval.  Returns -1 also for a singular lattice.    */
+int oracle_eval_lattice(int kind, int nx, int ny, int nz, int64_t ncoef,
+                        const void* coef, int coef_dtype, int padded,
+                        const double lattice[9], int64_t npos, const double* pos,
+                        double* v, double* g, double* l, double* h, int64_t ldo);
+
 /* Number of OpenMP threads an oracle_eval call uses. */
 int oracle_num_threads(void);
 

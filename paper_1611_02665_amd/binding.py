@@ -42,12 +42,14 @@ class bspl_table_info(ctypes.Structure):
                 ("n_splines", ctypes.c_int64), ("n_padded", ctypes.c_int64),
                 ("dtype", ctypes.c_int32), ("elem_bytes", ctypes.c_int32),
                 ("row_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
-                ("box", ctypes.c_double * 3), ("data", ctypes.c_void_p),
+                ("box", ctypes.c_double * 3), ("lattice", ctypes.c_double * 9),
+                ("data", ctypes.c_void_p),
                 ("scales", ctypes.c_void_p)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["box"] = tuple(self.box)
+        d["lattice"] = tuple(self.lattice)
         return d
 
 
@@ -73,6 +75,8 @@ _SIGS = {
     "spline_layout_query": (_int, [_int, _int, _int, _i64, _int, _P(bspl_table_info)]),
     "spline_table_create": (_int, [_P(_vp), _int, _int, _int, _i64, _vp, _int,
                                    _P(ctypes.c_double), _u32, _vp]),
+    "spline_table_create_lattice": (_int, [_P(_vp), _int, _int, _int, _i64, _vp, _int,
+                                           _P(ctypes.c_double), _u32, _vp]),
     "spline_table_destroy": (_int, [_vp]),
     "spline_table_info": (_int, [_vp, _P(bspl_table_info)]),
     "spline_eval_v": (_int, [_vp, _i64, _vp, _vp, _i64, _vp]),
@@ -163,6 +167,19 @@ def spline_table_create(nx, ny, nz, n_splines, coefs, dtype="f32", box=None, fla
     _check(lib.spline_table_create(ctypes.byref(h), nx, ny, nz, n_splines, _ptr(coefs),
                                    _enum(dtype, DTYPES), bx, flags, _stream(stream)),
            "spline_table_create")
+    return h.value
+
+
+def spline_table_create_lattice(nx, ny, nz, n_splines, coefs, lattice, dtype="f32", flags=0,
+                                stream=None) -> int:
+    """Table on a general cell; ``lattice`` holds the cell vectors as rows."""
+    h = ctypes.c_void_p()
+    lat = (ctypes.c_double * 9)(*[float(x) for x in list(lattice[0]) + list(lattice[1])
+                                  + list(lattice[2])]) if len(lattice) == 3 else \
+        (ctypes.c_double * 9)(*[float(x) for x in lattice])
+    _check(lib.spline_table_create_lattice(ctypes.byref(h), nx, ny, nz, n_splines, _ptr(coefs),
+                                           _enum(dtype, DTYPES), lat, flags, _stream(stream)),
+           "spline_table_create_lattice")
     return h.value
 
 

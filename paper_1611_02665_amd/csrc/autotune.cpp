@@ -273,7 +273,8 @@ bspl_status spline_autotune(const bspl_table* t, bspl_kind kind, int64_t npos,
     if (st != BSPL_OK) return st;
     char key[256];
     const int32_t nc[3] = {t->info.nx, t->info.ny, t->info.nz};
-    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos, "single");
+    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos,
+               t->lattice ? "single-lattice" : "single");
     st = record_wisdom(wisdom_path, key, bt, us);
     if (best) *best = bt;
     return st;

@@ -87,6 +87,14 @@ Bindings current_bindings(const bspl_plan& p) {
     return b;
 }
 
+// A plan with any non-box cell runs the lattice form of the kernel for all
+// of its tables (a box is a lattice with a diagonal map).
+int plan_lattice(const bspl_plan& p) {
+    for (int i = 0; i < p.ntables; ++i)
+        if (p.tables[i]->lattice) return 1;
+    return 0;
+}
+
 void batch_key(const bspl_plan& p, char* buf, size_t n) {
     std::string k;
     for (int i = 0; i < p.ntables; ++i) {
@@ -94,7 +102,7 @@ void batch_key(const bspl_plan& p, char* buf, size_t n) {
         const bspl_table_info& in = p.tables[i]->info;
         const int32_t nc[3] = {in.nx, in.ny, in.nz};
         wisdom_key(part, sizeof part, in.dtype, p.kind, in.n_splines, nc, p.npos[i],
-                   i == 0 ? "batch" : "");
+                   i == 0 ? (plan_lattice(p) ? "batch-lattice" : "batch") : "");
         k += (i == 0 ? "" : "+");
         k += part;
     }
@@ -190,7 +198,7 @@ hipKernelNodeParams order_params(bspl_plan* p, int i) {
 
 // Graph: [one ordering node per table (order > 0)] -> one evaluation node.
 bspl_status instantiate(bspl_plan* p) {
-    const void* fn = multi_kernel_ptr(p->dtype, p->kind, p->tile.vw);
+    const void* fn = multi_kernel_ptr(p->dtype, p->kind, p->tile.vw, plan_lattice(*p));
     if (!fn) return fail(BSPL_EINVAL, "no batched kernel for vw=%d", p->tile.vw);
     BSPL_HIP(hipGraphCreate(&p->graph, 0));
     std::vector<hipGraphNode_t> deps;
@@ -331,7 +339,8 @@ bspl_status spline_batch_execute(bspl_plan* p, void* stream) {
         }
         hipKernelNodeParams kp{};
         void* params[] = {&p->args};
-        kp.func = const_cast<void*>(multi_kernel_ptr(p->dtype, p->kind, p->tile.vw));
+        kp.func = const_cast<void*>(multi_kernel_ptr(p->dtype, p->kind, p->tile.vw,
+                                                     plan_lattice(*p)));
         kp.gridDim = dim3((unsigned)grid_for(p->args, p->tile));
         kp.blockDim = dim3(64 * p->tile.wx * p->tile.wy);
         kp.kernelParams = params;

@@ -140,11 +140,10 @@ __device__ __forceinline__ float basis_weight(int r, float t) {
     return ((c3 * t + c2) * t + c1) * t + c0;
 }
 
-// Cell location of one coordinate in FP64.  Returns false for a non-finite
-// input.  A position with no fraction bits left (|u| >= 2^50) is placed on
-// grid point 0.
-__device__ __forceinline__ bool locate(double x, double inv_delta, int n, int& i0, float& t) {
-    const double u = x * inv_delta;
+// Cell location of one grid coordinate u (FP64).  Returns false for a
+// non-finite input.  A position with no fraction bits left (|u| >= 2^50) is
+// placed on grid point 0.
+__device__ __forceinline__ bool locate(double u, int n, int& i0, float& t) {
     if (!__builtin_isfinite(u)) {
         i0 = 0;
         t = 0.f;
@@ -177,23 +176,65 @@ template <typename T, int VW> struct Depth {
 // Steps 1-3 (and the scale of step 4) for one work unit: on return acc holds
 // the unit's outputs for splines [n0, n0 + VW) of lane `lane`, of which
 // `valid` (if positive) are real splines.
-template <typename T, int VW, int KIND, int DEPTH = Depth<T, VW>::value>
+// Select element i (0..8) of nine uniform values without indexing memory.
+template <typename V>
+__device__ __forceinline__ V pick9(const V (&m)[9], int i) {
+    V r = m[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) r = i == k ? m[k] : r;
+    return r;
+}
+
+// Upper-triangle component k (xx, xy, xz, yy, yz, zz) as an index pair.
+__device__ __forceinline__ int sym_row(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
+__device__ __forceinline__ int sym_col(int k) { return k < 3 ? k : (k < 5 ? k - 2 : 2); }
+
+// Coefficient of grid-space Hessian component q in Cartesian component k:
+// H_r[a][b] = sum_{d,e} M[d][a] M[e][b] H_u[d][e], with the symmetric
+// off-diagonal pairs of H_u folded together.
+__device__ __forceinline__ float hess_coef(const float (&m)[9], int k, int q) {
+    const int a = sym_row(k), b = sym_col(k), dd = sym_row(q), e = sym_col(q);
+    float c = pick9(m, 3 * dd + a) * pick9(m, 3 * e + b);
+    if (dd != e) c = fmaf(pick9(m, 3 * e + a), pick9(m, 3 * dd + b), c);
+    return c;
+}
+
+// Lattice tables evaluate VGL with the whole grid-space Hessian, which the
+// Laplacian needs once the axes are not orthogonal.
+template <int KIND, int LAT> struct Internal {
+    static constexpr int kind = (LAT && KIND == BSPL_VGL) ? BSPL_VGH : KIND;
+};
+
+template <typename T, int VW, int KIND, int LAT, int DEPTH = Depth<T, VW>::value>
 __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, int lane,
-                                          float (&acc)[Shape<KIND>::nout][VW], int& n0_out,
+                                          float (&out)[Shape<KIND>::nout][VW], int& n0_out,
                                           int& valid_out) {
     constexpr int EB = Elem<T>::bytes;
-    constexpr int NOUT = Shape<KIND>::nout;
-    constexpr int NY = Shape<KIND>::ny;
+    constexpr int KI = Internal<KIND, LAT>::kind;  // what is accumulated
+    constexpr int NOUT = Shape<KI>::nout;
+    constexpr int NY = Shape<KI>::ny;
 
-    // 1. cell index and fraction: lane d handles dimension d
+    // 1. cell index and fraction: lane d handles grid axis d,
+    //    u_d = sum_a M[d][a] r_a in FP64 (a box has M diagonal)
     int my_i0 = 0;
     float my_t = 0.f;
     int my_bad = 0;
     if (lane < 3) {
-        const double x = d.pos[(int64_t)lane * d.npos + p];
-        const double invd = lane == 0 ? d.inv_delta[0] : (lane == 1 ? d.inv_delta[1] : d.inv_delta[2]);
+        double u;
+        if constexpr (LAT) {
+            const double x = d.pos[p];
+            const double y = d.pos[d.npos + p];
+            const double z = d.pos[2 * d.npos + p];
+            const double mx = lane == 0 ? d.M[0][0] : (lane == 1 ? d.M[1][0] : d.M[2][0]);
+            const double my = lane == 0 ? d.M[0][1] : (lane == 1 ? d.M[1][1] : d.M[2][1]);
+            const double mz = lane == 0 ? d.M[0][2] : (lane == 1 ? d.M[1][2] : d.M[2][2]);
+            u = __builtin_fma(mx, x, __builtin_fma(my, y, mz * z));
+        } else {  // a box: M is diagonal
+            const double m = lane == 0 ? d.M[0][0] : (lane == 1 ? d.M[1][1] : d.M[2][2]);
+            u = d.pos[(int64_t)lane * d.npos + p] * m;
+        }
         const int n = lane == 0 ? d.ncell[0] : (lane == 1 ? d.ncell[1] : d.ncell[2]);
-        my_bad = locate(x, invd, n, my_i0, my_t) ? 0 : 1;
+        my_bad = locate(u, n, my_i0, my_t) ? 0 : 1;
     }
     const int i0 = __builtin_amdgcn_readlane(my_i0, 0);
     const int j0 = __builtin_amdgcn_readlane(my_i0, 1);
@@ -208,7 +249,9 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
         const int dim = lane >= 24 ? 2 : (lane >= 12 ? 1 : 0);
         const int r = lane - 12 * dim;
         const float t = dim == 0 ? tx : (dim == 1 ? ty : tz);
-        const float s = dim == 0 ? d.inv_delta_f[0] : (dim == 1 ? d.inv_delta_f[1] : d.inv_delta_f[2]);
+        // a box folds 1/Delta into the derivative weights; a lattice keeps
+        // grid units and transforms the derivatives at the end
+        const float s = LAT ? 1.f : (dim == 0 ? d.Mf[0][0] : (dim == 1 ? d.Mf[1][1] : d.Mf[2][2]));
         wv = basis_weight(r, t);
         wv *= r >= 8 ? s * s : (r >= 4 ? s : 1.f);
         if (bad) wv = __builtin_nanf("");
@@ -219,7 +262,7 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
         ax[m] = bcast(wv, m);
         ay[m] = bcast(wv, 12 + m);
         az[m] = bcast(wv, 24 + m);
-        if constexpr (KIND != BSPL_V) {
+        if constexpr (KI != BSPL_V) {
             dax[m] = bcast(wv, 4 + m);
             d2ax[m] = bcast(wv, 8 + m);
             day[m] = bcast(wv, 16 + m);
@@ -250,6 +293,7 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
         for (int k = 0; k < 4; ++k) ring[slot][k] = RowT::load(base + (go + (uint32_t)k * d.row_bytes));
     };
 
+    float acc[NOUT][VW];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o)
 #pragma unroll
@@ -279,7 +323,7 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
             s0 = fmaf(az[2], q[2][e], s0);
             s0 = fmaf(az[3], q[3][e], s0);
             Y[0][e] = fmaf(ay[j], s0, Y[0][e]);
-            if constexpr (KIND != BSPL_V) {
+            if constexpr (KI != BSPL_V) {
                 float s1 = daz[0] * q[0][e];
                 s1 = fmaf(daz[1], q[1][e], s1);
                 s1 = fmaf(daz[2], q[2][e], s1);
@@ -291,7 +335,7 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
                 Y[1][e] = fmaf(day[j], s0, Y[1][e]);   // d/dy
                 Y[2][e] = fmaf(d2ay[j], s0, Y[2][e]);  // d2/dy2
                 Y[3][e] = fmaf(ay[j], s1, Y[3][e]);    // d/dz
-                if constexpr (KIND == BSPL_VGH) {
+                if constexpr (KI == BSPL_VGH) {
                     Y[4][e] = fmaf(day[j], s1, Y[4][e]);  // d2/dydz
                     Y[5][e] = fmaf(ay[j], s2, Y[5][e]);   // d2/dz2
                 } else {
@@ -303,14 +347,14 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
 #pragma unroll
             for (int e = 0; e < VW; ++e) {
                 acc[0][e] = fmaf(ax[i], Y[0][e], acc[0][e]);  // v
-                if constexpr (KIND == BSPL_VGL) {
+                if constexpr (KI == BSPL_VGL) {
                     acc[1][e] = fmaf(dax[i], Y[0][e], acc[1][e]);  // gx
                     acc[2][e] = fmaf(ax[i], Y[1][e], acc[2][e]);   // gy
                     acc[3][e] = fmaf(ax[i], Y[3][e], acc[3][e]);   // gz
                     acc[4][e] = fmaf(d2ax[i], Y[0][e], acc[4][e]); // lap: xx
                     acc[4][e] = fmaf(ax[i], Y[2][e] + Y[4][e], acc[4][e]);  // + yy + zz
                 }
-                if constexpr (KIND == BSPL_VGH) {
+                if constexpr (KI == BSPL_VGH) {
                     acc[1][e] = fmaf(dax[i], Y[0][e], acc[1][e]);  // gx
                     acc[2][e] = fmaf(ax[i], Y[1][e], acc[2][e]);   // gy
                     acc[3][e] = fmaf(ax[i], Y[3][e], acc[3][e]);   // gz
@@ -339,7 +383,58 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
         }
     }
 
-    // 4a. per-spline scale of reduced-precision tables
+    // 4a. lattice tables: grid-space derivatives to Cartesian ones,
+    //     g_r = M^T g_u and H_r = M^T H_u M (L = trace H_r)
+    constexpr int NO = Shape<KIND>::nout;
+    if constexpr (LAT && KIND != BSPL_V) {
+        float m[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) m[k] = d.Mf[k / 3][k % 3];
+        // lane 6k + q holds the coefficient of H_u component q in H_r component k
+        float hc = 0.f;
+        if (lane < 36) hc = hess_coef(m, lane / 6, lane % 6);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            out[0][e] = acc[0][e];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                out[1 + a][e] = fmaf(m[a], acc[1][e], fmaf(m[3 + a], acc[2][e], m[6 + a] * acc[3][e]));
+        }
+        if constexpr (KIND == BSPL_VGH) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                float c[6];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) c[q] = bcast(hc, 6 * k + q);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    float h = 0.f;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) h = fmaf(c[q], acc[4 + q][e], h);
+                    out[4 + k][e] = h;
+                }
+            }
+        } else {  // VGL: the Laplacian sums the diagonal components k = 0, 3, 5
+            float c[6];
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+                c[q] = bcast(hc, q) + bcast(hc, 18 + q) + bcast(hc, 30 + q);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                float h = 0.f;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) h = fmaf(c[q], acc[4 + q][e], h);
+                out[4][e] = h;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) out[o][e] = acc[o][e];
+    }
+
+    // 4b. per-spline scale of reduced-precision tables
     n0_out = n0;
     valid_out = valid;
     if (valid <= 0) return;
@@ -348,18 +443,18 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
 #pragma unroll
         for (int e = 0; e < VW; ++e) sc[e] = d.scales[n0 + e];
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o)
+        for (int o = 0; o < NO; ++o)
 #pragma unroll
-            for (int e = 0; e < VW; ++e) acc[o][e] *= sc[e];
+            for (int e = 0; e < VW; ++e) out[o][e] *= sc[e];
     }
 }
 
-// One work unit: evaluate, then 4b. write the 1, 5 or 10 SoA output rows.
-template <typename T, int VW, int KIND>
+// One work unit: evaluate, then write the 1, 5 or 10 SoA output rows.
+template <typename T, int VW, int KIND, int LAT>
 __device__ __forceinline__ void eval_unit(const TableDesc& d, int p, int chunk, int lane) {
     float acc[Shape<KIND>::nout][VW];
     int n0, valid;
-    eval_core<T, VW, KIND>(d, p, chunk, lane, acc, n0, valid);
+    eval_core<T, VW, KIND, LAT>(d, p, chunk, lane, acc, n0, valid);
     if (valid <= 0) return;
     const bool vec = d.vec_store != 0;
     const int64_t ldo = d.ldo;
@@ -391,7 +486,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t total) {
 // spline tiles by wy positions of one table; blocks are numbered table by
 // table, positions outer, tiles inner.  With fewer workgroups than blocks
 // (persistent launch) each workgroup strides over the blocks.
-template <typename T, int VW, int KIND, int MAXT>
+template <typename T, int VW, int KIND, int MAXT, int LAT>
 __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -412,7 +507,7 @@ __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
         const int q = pg * a.wy + wyi;
         if (chunk < d.nchunks && q < d.npos) {
             const int p = d.perm ? __builtin_amdgcn_readfirstlane(d.perm[q]) : q;
-            eval_unit<T, VW, KIND>(d, p, chunk, lane);
+            eval_unit<T, VW, KIND, LAT>(d, p, chunk, lane);
         }
     }
 }
@@ -428,7 +523,7 @@ __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
 // reduced across the wavefront with shuffles and across the workgroup in LDS,
 // in a fixed order, so the result is deterministic.  The N output rows are
 // never written: a position reads its N-entry ainv row instead.
-template <typename T, int VW, int KIND>
+template <typename T, int VW, int KIND, int LAT>
 __global__ void __launch_bounds__(512) ratio_kernel(const TableDesc d, const float* ainv,
                                                     int64_t ld_ainv, double* out) {
     constexpr int NOUT = Shape<KIND>::nout;
@@ -444,7 +539,7 @@ __global__ void __launch_bounds__(512) ratio_kernel(const TableDesc d, const flo
         for (int c = wave; c < d.nchunks; c += W) {
             float acc[NOUT][VW];
             int n0, valid;
-            eval_core<T, VW, KIND>(d, p, c, lane, acc, n0, valid);
+            eval_core<T, VW, KIND, LAT>(d, p, c, lane, acc, n0, valid);
             if (valid > 0) {
                 float a[VW];
                 const float* row = ainv + (int64_t)p * ld_ainv + n0;
@@ -477,31 +572,36 @@ __global__ void __launch_bounds__(512) ratio_kernel(const TableDesc d, const flo
     }
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, int LAT>
 const void* pick_ratio(int vw) {
     if constexpr (Elem<T>::bytes == 4) {
         switch (vw) {
-        case 1: return (const void*)&ratio_kernel<T, 1, KIND>;
-        case 2: return (const void*)&ratio_kernel<T, 2, KIND>;
-        case 4: return (const void*)&ratio_kernel<T, 4, KIND>;
+        case 1: return (const void*)&ratio_kernel<T, 1, KIND, LAT>;
+        case 2: return (const void*)&ratio_kernel<T, 2, KIND, LAT>;
+        case 4: return (const void*)&ratio_kernel<T, 4, KIND, LAT>;
         }
     } else {
         switch (vw) {
-        case 2: return (const void*)&ratio_kernel<T, 2, KIND>;
-        case 4: return (const void*)&ratio_kernel<T, 4, KIND>;
-        case 8: return (const void*)&ratio_kernel<T, 8, KIND>;
+        case 2: return (const void*)&ratio_kernel<T, 2, KIND, LAT>;
+        case 4: return (const void*)&ratio_kernel<T, 4, KIND, LAT>;
+        case 8: return (const void*)&ratio_kernel<T, 8, KIND, LAT>;
         }
     }
     return nullptr;
 }
 
-const void* ratio_kernel_for(int dtype, int kind, int vw) {
-#define BSPL_RKINDS(T)                                        \
-    switch (kind) {                                           \
-    case BSPL_V: return pick_ratio<T, BSPL_V>(vw);            \
-    case BSPL_VGL: return pick_ratio<T, BSPL_VGL>(vw);        \
-    case BSPL_VGH: return pick_ratio<T, BSPL_VGH>(vw);        \
-    }                                                         \
+template <typename T, int KIND>
+const void* pick_ratio_lat(int vw, int lattice) {
+    return lattice ? pick_ratio<T, KIND, 1>(vw) : pick_ratio<T, KIND, 0>(vw);
+}
+
+const void* ratio_kernel_for(int dtype, int kind, int vw, int lattice) {
+#define BSPL_RKINDS(T)                                                    \
+    switch (kind) {                                                       \
+    case BSPL_V: return pick_ratio_lat<T, BSPL_V>(vw, lattice);           \
+    case BSPL_VGL: return pick_ratio_lat<T, BSPL_VGL>(vw, lattice);       \
+    case BSPL_VGH: return pick_ratio_lat<T, BSPL_VGH>(vw, lattice);       \
+    }                                                                     \
     return nullptr;
     switch (dtype) {
     case BSPL_F32: { BSPL_RKINDS(F32) }
@@ -512,32 +612,37 @@ const void* ratio_kernel_for(int dtype, int kind, int vw) {
     return nullptr;
 }
 
-template <typename T, int KIND, int MAXT>
+template <typename T, int KIND, int MAXT, int LAT>
 const void* pick_kernel(int vw) {
     if constexpr (Elem<T>::bytes == 4) {
         switch (vw) {
-        case 1: return (const void*)&eval_kernel<T, 1, KIND, MAXT>;
-        case 2: return (const void*)&eval_kernel<T, 2, KIND, MAXT>;
-        case 4: return (const void*)&eval_kernel<T, 4, KIND, MAXT>;
+        case 1: return (const void*)&eval_kernel<T, 1, KIND, MAXT, LAT>;
+        case 2: return (const void*)&eval_kernel<T, 2, KIND, MAXT, LAT>;
+        case 4: return (const void*)&eval_kernel<T, 4, KIND, MAXT, LAT>;
         }
     } else {
         switch (vw) {
-        case 2: return (const void*)&eval_kernel<T, 2, KIND, MAXT>;
-        case 4: return (const void*)&eval_kernel<T, 4, KIND, MAXT>;
-        case 8: return (const void*)&eval_kernel<T, 8, KIND, MAXT>;
+        case 2: return (const void*)&eval_kernel<T, 2, KIND, MAXT, LAT>;
+        case 4: return (const void*)&eval_kernel<T, 4, KIND, MAXT, LAT>;
+        case 8: return (const void*)&eval_kernel<T, 8, KIND, MAXT, LAT>;
         }
     }
     return nullptr;
 }
 
+template <typename T, int KIND, int MAXT>
+const void* pick_kernel_lat(int vw, int lattice) {
+    return lattice ? pick_kernel<T, KIND, MAXT, 1>(vw) : pick_kernel<T, KIND, MAXT, 0>(vw);
+}
+
 template <int MAXT>
-const void* kernel_for(int dtype, int kind, int vw) {
-#define BSPL_KINDS(T)                                              \
-    switch (kind) {                                                \
-    case BSPL_V: return pick_kernel<T, BSPL_V, MAXT>(vw);          \
-    case BSPL_VGL: return pick_kernel<T, BSPL_VGL, MAXT>(vw);      \
-    case BSPL_VGH: return pick_kernel<T, BSPL_VGH, MAXT>(vw);      \
-    }                                                              \
+const void* kernel_for(int dtype, int kind, int vw, int lattice) {
+#define BSPL_KINDS(T)                                                      \
+    switch (kind) {                                                        \
+    case BSPL_V: return pick_kernel_lat<T, BSPL_V, MAXT>(vw, lattice);     \
+    case BSPL_VGL: return pick_kernel_lat<T, BSPL_VGL, MAXT>(vw, lattice); \
+    case BSPL_VGH: return pick_kernel_lat<T, BSPL_VGH, MAXT>(vw, lattice); \
+    }                                                                      \
     return nullptr;
     switch (dtype) {
     case BSPL_F32: { BSPL_KINDS(F32) }
@@ -574,21 +679,28 @@ bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
     a.xcd_remap = tile.order == 2 ? 1 : 0;
     const int64_t ygroups = (d.npos + tile.wy - 1) / tile.wy;
     a.total_groups = ygroups * d.xgroups;
-    return launch<1>(kernel_for<1>(t->info.dtype, kind, tile.vw), a, tile, s);
+    return launch<1>(kernel_for<1>(t->info.dtype, kind, tile.vw, d.lattice), a, tile, s);
+}
+
+static int any_lattice(const KernelArgs<kMaxTables>& a) {
+    for (int i = 0; i < a.ntables; ++i)
+        if (a.t[i].lattice) return 1;
+    return 0;
 }
 
 bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
                          const bspl_tile& tile, hipStream_t s) {
-    return launch<kMaxTables>(kernel_for<kMaxTables>(dtype, kind, tile.vw), a, tile, s);
+    return launch<kMaxTables>(kernel_for<kMaxTables>(dtype, kind, tile.vw, any_lattice(a)), a,
+                              tile, s);
 }
 
-const void* multi_kernel_ptr(int dtype, int kind, int vw) {
-    return kernel_for<kMaxTables>(dtype, kind, vw);
+const void* multi_kernel_ptr(int dtype, int kind, int vw, int lattice) {
+    return kernel_for<kMaxTables>(dtype, kind, vw, lattice);
 }
 
 bspl_status launch_ratio(const bspl_table* t, int kind, const TableDesc& d, const float* ainv,
                          int64_t ld_ainv, double* out, const bspl_tile& tile, hipStream_t s) {
-    const void* fn = ratio_kernel_for(t->info.dtype, kind, tile.vw);
+    const void* fn = ratio_kernel_for(t->info.dtype, kind, tile.vw, d.lattice);
     if (!fn) return fail(BSPL_EINVAL, "no ratio kernel for this dtype/kind/vw");
     if (d.npos <= 0) return BSPL_OK;
     int waves = tile.wx < d.nchunks ? tile.wx : d.nchunks;

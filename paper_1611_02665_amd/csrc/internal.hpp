@@ -10,6 +10,8 @@
 
 struct bspl_table {
     bspl_table_info info;   // data / scales point at d_table / d_scales
+    double grid_map[3][3];  // u = grid_map r: grid coordinates of a Cartesian position
+    int lattice = 0;        // 1 when the cell is not an axis-aligned box
     void* d_table = nullptr;
     float* d_scales = nullptr;
     int device = 0;
@@ -49,8 +51,9 @@ struct TableDesc {
     int64_t npos;
     int64_t ldo;
     int64_t groups_begin;     // first workgroup-block index of this table
-    double inv_delta[3];      // n_d / L_d
-    float inv_delta_f[3];
+    double M[3][3];           // grid coordinates u_d = sum_a M[d][a] r_a (box: n_d/L_d diagonal)
+    float Mf[3][3];           // the same in FP32, for derivative weights and transforms
+    int32_t lattice;          // 1: derivatives in grid units, then transformed by Mf
     int32_t ncell[3];
     uint32_t row_bytes;       // bytes between consecutive z rows
     uint32_t ystride;         // bytes between consecutive y planes
@@ -87,19 +90,22 @@ bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
 bspl_status launch_ratio(const bspl_table* t, int kind, const TableDesc& d, const float* ainv,
                          int64_t ld_ainv, double* out, const bspl_tile& tile, hipStream_t s);
 // Address of the batched kernel for a configuration (graph node building).
-const void* multi_kernel_ptr(int dtype, int kind, int vw);
+const void* multi_kernel_ptr(int dtype, int kind, int vw, int lattice);
 
 // Cell-ordering pre-pass (order_kernels.hip): perm[i] for i < npos.
 // OrderLaunch holds the launch shape and the argument values (args[] points
 // into the struct, so it must not be copied after order_launch_config).
+struct OrderMap {
+    double m[3][3];
+};
 struct OrderLaunch {
     const double* pos;
     int npos;
-    double idx, idy, idz;
+    OrderMap map;
     int nx, ny, nz;
     int32_t* perm;
     unsigned grid, block, shmem;
-    void* args[9];
+    void* args[7];
 };
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o);
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s);

@@ -29,9 +29,8 @@ __device__ __forceinline__ uint32_t spread3_4(uint32_t v) {  // 4 bits -> every 
     return v;
 }
 
-// Bin coordinate (0..15) of coordinate x on a periodic axis of n cells.
-__device__ __forceinline__ uint32_t bin16(double x, double inv_delta, int n) {
-    const double u = x * inv_delta;
+// Bin coordinate (0..15) of grid coordinate u on a periodic axis of n cells.
+__device__ __forceinline__ uint32_t bin16(double u, int n) {
     if (!__builtin_isfinite(u) || !(__builtin_fabs(u) < 1125899906842624.0)) return 0u;
     const double nd = (double)n;
     const double w = u - nd * __builtin_floor(u / nd);
@@ -40,8 +39,8 @@ __device__ __forceinline__ uint32_t bin16(double x, double inv_delta, int n) {
 }
 
 __global__ void __launch_bounds__(kOrderThreads) order_kernel(
-    const double* __restrict__ pos, int npos, double idx_, double idy_, double idz_, int nx,
-    int ny, int nz, int32_t* __restrict__ perm) {
+    const double* __restrict__ pos, int npos, const OrderMap map, int nx, int ny, int nz,
+    int32_t* __restrict__ perm) {
     __shared__ uint32_t count[kBins];
     __shared__ uint32_t wsum[kOrderThreads / 64];
     const int tid = threadIdx.x;
@@ -58,9 +57,11 @@ __global__ void __launch_bounds__(kOrderThreads) order_kernel(
         bin[r] = 0u;
         if (i < cnt) {
             const int p = base + i;
-            const uint32_t bx = bin16(pos[p], idx_, nx);
-            const uint32_t by = bin16(pos[(int64_t)npos + p], idy_, ny);
-            const uint32_t bz = bin16(pos[2 * (int64_t)npos + p], idz_, nz);
+            const double x = pos[p], y = pos[(int64_t)npos + p], z = pos[2 * (int64_t)npos + p];
+            const double* m = &map.m[0][0];
+            const uint32_t bx = bin16(m[0] * x + m[1] * y + m[2] * z, nx);
+            const uint32_t by = bin16(m[3] * x + m[4] * y + m[5] * z, ny);
+            const uint32_t bz = bin16(m[6] * x + m[7] * y + m[8] * z, nz);
             bin[r] = (spread3_4(bx) << 2) | (spread3_4(by) << 1) | spread3_4(bz);
         }
     }
@@ -110,9 +111,8 @@ __global__ void __launch_bounds__(kOrderThreads) order_kernel(
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o) {
     o->pos = d.pos;
     o->npos = (int)d.npos;
-    o->idx = d.inv_delta[0];
-    o->idy = d.inv_delta[1];
-    o->idz = d.inv_delta[2];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) o->map.m[a][b] = d.M[a][b];
     o->nx = d.ncell[0];
     o->ny = d.ncell[1];
     o->nz = d.ncell[2];
@@ -120,8 +120,8 @@ void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o) {
     o->grid = (unsigned)((d.npos + kOrderChunk - 1) / kOrderChunk);
     o->block = kOrderThreads;
     o->shmem = 0;
-    void* a[] = {&o->pos, &o->npos, &o->idx, &o->idy, &o->idz, &o->nx, &o->ny, &o->nz, &o->perm};
-    for (int i = 0; i < 9; ++i) o->args[i] = a[i];
+    void* a[] = {&o->pos, &o->npos, &o->map, &o->nx, &o->ny, &o->nz, &o->perm};
+    for (int i = 0; i < 7; ++i) o->args[i] = a[i];
 }
 
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s) {

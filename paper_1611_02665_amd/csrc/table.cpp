@@ -79,11 +79,13 @@ bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, floa
     d.ldo = ldo;
     d.groups_begin = 0;
     const int ncell[3] = {in.nx, in.ny, in.nz};
-    for (int k = 0; k < 3; ++k) {
-        d.ncell[k] = ncell[k];
-        d.inv_delta[k] = (double)ncell[k] / in.box[k];
-        d.inv_delta_f[k] = (float)d.inv_delta[k];
-    }
+    for (int k = 0; k < 3; ++k) d.ncell[k] = ncell[k];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            d.M[a][b] = t->grid_map[a][b];
+            d.Mf[a][b] = (float)t->grid_map[a][b];
+        }
+    d.lattice = t->lattice;
     d.row_bytes = (uint32_t)in.row_bytes;
     d.ystride = (uint32_t)((int64_t)in.pz * in.row_bytes);
     d.xstride = (uint32_t)((int64_t)in.py * in.pz * in.row_bytes);
@@ -148,13 +150,57 @@ bspl_status spline_layout_query(int nx, int ny, int nz, int64_t n_splines, bspl_
     if (span >= 4294967296.0)
         return fail(BSPL_EUNSUPPORTED, "one cell's row block spans %.3g bytes (>= 4 GiB)", span);
     i.box[0] = i.box[1] = i.box[2] = 1.0;
+    i.lattice[0] = i.lattice[4] = i.lattice[8] = 1.0;
     *out = i;
     return BSPL_OK;
 }
 
-bspl_status spline_table_create(bspl_table** out, int nx, int ny, int nz, int64_t n_splines,
-                                const float* coefs, bspl_dtype dtype, const double box[3],
-                                unsigned flags, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Grid map of a cell with vectors a_i = lattice[3i..3i+2]: the grid
+// coordinate of r along axis d is u_d = n_d * (r A^-1)_d, so
+// M[d][a] = n_d * (A^-1)[a][d].  Fails for a singular or non-finite cell.
+bspl_status grid_map_of(const double lat[9], const int n[3], double M[3][3], int* is_lattice) {
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(lat[k])) return fail(BSPL_EINVAL, "lattice[%d] is not finite", k);
+    const double a00 = lat[0], a01 = lat[1], a02 = lat[2], a10 = lat[3], a11 = lat[4],
+                 a12 = lat[5], a20 = lat[6], a21 = lat[7], a22 = lat[8];
+    const double c00 = a11 * a22 - a12 * a21, c01 = a12 * a20 - a10 * a22,
+                 c02 = a10 * a21 - a11 * a20;
+    const double det = a00 * c00 + a01 * c01 + a02 * c02;
+    double norms = 1.0;
+    for (int i = 0; i < 3; ++i)
+        norms *= std::sqrt(lat[3 * i] * lat[3 * i] + lat[3 * i + 1] * lat[3 * i + 1] +
+                           lat[3 * i + 2] * lat[3 * i + 2]);
+    if (!(std::fabs(det) > 1e-12 * norms) || !(det > 0.0 || det < 0.0))
+        return fail(BSPL_EINVAL, "the cell vectors are (nearly) linearly dependent");
+    // inverse by the adjugate: inv[a][b] = cofactor[b][a] / det
+    double inv[3][3];
+    inv[0][0] = c00 / det;
+    inv[1][0] = c01 / det;
+    inv[2][0] = c02 / det;
+    inv[0][1] = (a02 * a21 - a01 * a22) / det;
+    inv[1][1] = (a00 * a22 - a02 * a20) / det;
+    inv[2][1] = (a01 * a20 - a00 * a21) / det;
+    inv[0][2] = (a01 * a12 - a02 * a11) / det;
+    inv[1][2] = (a02 * a10 - a00 * a12) / det;
+    inv[2][2] = (a00 * a11 - a01 * a10) / det;
+    int off = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+            if (i != j && lat[3 * i + j] != 0.0) off = 1;
+    for (int dd = 0; dd < 3; ++dd)
+        for (int a = 0; a < 3; ++a)
+            M[dd][a] = off ? n[dd] * inv[a][dd] : (a == dd ? n[dd] / lat[4 * dd] : 0.0);
+    *is_lattice = off;
+    return BSPL_OK;
+}
+
+bspl_status create_table(bspl_table** out, int nx, int ny, int nz, int64_t n_splines,
+                         const float* coefs, bspl_dtype dtype, const double lat[9],
+                         unsigned flags, void* stream) {
     if (!out) return fail(BSPL_EINVAL, "out is NULL");
     *out = nullptr;
     if (!coefs) return fail(BSPL_EINVAL, "coefs is NULL");
@@ -163,13 +209,15 @@ bspl_status spline_table_create(bspl_table** out, int nx, int ny, int nz, int64_
     bspl_table_info info{};
     bspl_status st = spline_layout_query(nx, ny, nz, n_splines, dtype, &info);
     if (st != BSPL_OK) return st;
-    if (box) {
-        for (int k = 0; k < 3; ++k) {
-            if (!(box[k] > 0.0) || !std::isfinite(box[k]))
-                return fail(BSPL_EINVAL, "box[%d] = %g must be finite and > 0", k, box[k]);
-            info.box[k] = box[k];
-        }
-    }
+    const int ncell[3] = {nx, ny, nz};
+    double gm[3][3];
+    int is_lattice = 0;
+    st = grid_map_of(lat, ncell, gm, &is_lattice);
+    if (st != BSPL_OK) return st;
+    for (int k = 0; k < 9; ++k) info.lattice[k] = lat[k];
+    for (int k = 0; k < 3; ++k)
+        info.box[k] = std::sqrt(lat[3 * k] * lat[3 * k] + lat[3 * k + 1] * lat[3 * k + 1] +
+                                lat[3 * k + 2] * lat[3 * k + 2]);
     const bool padded = (flags & BSPL_COEFS_PADDED) != 0;
     const int64_t src_elems = padded ? (int64_t)info.px * info.py * info.pz * n_splines
                                      : (int64_t)nx * ny * nz * n_splines;
@@ -178,6 +226,9 @@ bspl_status spline_table_create(bspl_table** out, int nx, int ny, int nz, int64_
     bspl_table* t = new (std::nothrow) bspl_table();
     if (!t) return fail(BSPL_ENOMEM, "host allocation");
     t->info = info;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) t->grid_map[a][b] = gm[a][b];
+    t->lattice = is_lattice;
     (void)hipGetDevice(&t->device);
     hipError_t e = hipMalloc(&t->d_table, (size_t)info.table_bytes);
     if (e != hipSuccess) {
@@ -218,6 +269,36 @@ bspl_status spline_table_create(bspl_table** out, int nx, int ny, int nz, int64_
     return BSPL_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+bspl_status spline_table_create(bspl_table** out, int nx, int ny, int nz, int64_t n_splines,
+                                const float* coefs, bspl_dtype dtype, const double box[3],
+                                unsigned flags, void* stream) {
+    double lat[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    if (box) {
+        for (int k = 0; k < 3; ++k) {
+            if (!(box[k] > 0.0) || !std::isfinite(box[k])) {
+                if (out) *out = nullptr;
+                return fail(BSPL_EINVAL, "box[%d] = %g must be finite and > 0", k, box[k]);
+            }
+            lat[4 * k] = box[k];
+        }
+    }
+    return create_table(out, nx, ny, nz, n_splines, coefs, dtype, lat, flags, stream);
+}
+
+bspl_status spline_table_create_lattice(bspl_table** out, int nx, int ny, int nz,
+                                        int64_t n_splines, const float* coefs, bspl_dtype dtype,
+                                        const double lattice[9], unsigned flags, void* stream) {
+    if (!lattice) {
+        if (out) *out = nullptr;
+        return fail(BSPL_EINVAL, "lattice is NULL");
+    }
+    return create_table(out, nx, ny, nz, n_splines, coefs, dtype, lattice, flags, stream);
+}
+
 bspl_status spline_table_destroy(bspl_table* t) {
     if (!t) return BSPL_OK;
     if (t->d_table) (void)hipFree(t->d_table);
@@ -238,7 +319,8 @@ bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos
     if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
     char key[256];
     const int32_t nc[3] = {t->info.nx, t->info.ny, t->info.nz};
-    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos, "single");
+    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos,
+               t->lattice ? "single-lattice" : "single");
     bspl_tile tile;
     if (wisdom_lookup(key, &tile) && tile_valid(tile, t->info.dtype)) {
         *out = tile;

@@ -92,6 +92,29 @@ def test_create_validates_before_touching_the_device():
         == B.BSPL_EINVAL
 
 
+def test_create_lattice_validates_before_touching_the_device():
+    h = ctypes.c_void_p(1234)
+    coefs = (ctypes.c_float * 8)()
+    f = B.lib.spline_table_create_lattice
+    assert f(ctypes.byref(h), 1, 1, 1, 8, coefs, 0, None, 0, None) == B.BSPL_EINVAL
+    assert h.value is None
+    assert "lattice" in B.spline_last_error()
+    # a2 = 2 a1: the cell vectors span a plane only
+    flat = (ctypes.c_double * 9)(1.0, 0.5, 0.0, 2.0, 1.0, 0.0, 0.0, 0.0, 1.0)
+    assert f(ctypes.byref(h), 1, 1, 1, 8, coefs, 0, flat, 0, None) == B.BSPL_EINVAL
+    assert "linearly dependent" in B.spline_last_error()
+    zero = (ctypes.c_double * 9)()
+    assert f(ctypes.byref(h), 1, 1, 1, 8, coefs, 0, zero, 0, None) == B.BSPL_EINVAL
+    inf = (ctypes.c_double * 9)(1.0, 0.0, 0.0, 0.0, float("inf"), 0.0, 0.0, 0.0, 1.0)
+    assert f(ctypes.byref(h), 1, 1, 1, 8, coefs, 0, inf, 0, None) == B.BSPL_EINVAL
+    assert "not finite" in B.spline_last_error()
+    ok = (ctypes.c_double * 9)(1.0, 0.0, 0.0, -0.5, 0.8, 0.0, 0.0, 0.0, 1.6)
+    # valid cell, but bad sizes / dtype are still rejected first
+    assert f(ctypes.byref(h), 0, 1, 1, 8, coefs, 0, ok, 0, None) == B.BSPL_EINVAL
+    assert f(ctypes.byref(h), 1, 1, 1, 8, coefs, 9, ok, 0, None) == B.BSPL_EINVAL
+    assert f(None, 1, 1, 1, 8, coefs, 0, ok, 0, None) == B.BSPL_EINVAL
+
+
 def test_tile_struct_matches_header():
     text = open(HEADER).read()
     body = text[text.index("typedef struct {\n    int32_t vw;"):]

@@ -1,0 +1,203 @@
+"""GPU parity on general (non-orthorhombic) cells, through the C ABI.
+
+Reference: the oracle's lattice evaluator (grid coordinates u = n (r A^-1),
+derivatives carried to Cartesian ones by the chain rule).  Same bar as the
+box tables: per component, max |gpu - oracle| / max |oracle| <= 1e-5 for
+FP32 tables and for FP16/BF16 tables against the oracle on the dequantised
+coefficients.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import assert_canary, assert_close, dequantized, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1611_02665_amd import binding as B  # noqa: E402
+
+HEX = np.array([[1.0, 0.0, 0.0], [-0.5, np.sqrt(3) / 2, 0.0], [0.0, 0.0, 1.6]])
+TRICLINIC = np.array([[1.1, 0.1, -0.2], [0.3, 0.9, 0.15], [-0.25, 0.2, 1.3]])
+CELLS = {"hex": HEX, "triclinic": TRICLINIC}
+
+
+def cell_positions(npos, lattice, stream, lo=-2.0, hi=3.0):
+    """Positions r = s A with fractional coordinates s uniform in [lo, hi)."""
+    s = synth.positions(npos, stream=stream) * (hi - lo) + lo
+    return np.ascontiguousarray(lattice.T @ s)
+
+
+class LatticeTable:
+    def __init__(self, coef, lattice, dtype="f32"):
+        nx, ny, nz, n = coef.shape
+        self.h = B.spline_table_create_lattice(nx, ny, nz, n,
+                                               np.ascontiguousarray(coef, np.float32),
+                                               lattice, dtype)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        B.spline_table_destroy(self.h)
+
+
+def _tiles(dtype):
+    vws = (1, 2, 4) if dtype == "f32" else (2, 4, 8)
+    shapes = [(1, 1), (4, 1), (1, 4), (2, 2), (8, 1)]
+    i = 0
+    for vw in vws:
+        for wx, wy in shapes:
+            yield (vw, wx, wy, 0 if i % 2 else 5, i % 3)
+            i += 1
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # N = 300 leaves a ragged last spline tile for every vector width
+    return synth.coef_table(7, 9, 5, 300, stream=81)
+
+
+@pytest.mark.parametrize("cell", sorted(CELLS))
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_lattice_tiles_and_kinds(ragged, cell, dtype):
+    A = CELLS[cell]
+    pos = cell_positions(37, A, stream=82)
+    deq = dequantized(ragged, dtype)
+    refs = {k: oracle.evaluate_lattice(k, deq, pos, A) for k in ("v", "vgl", "vgh")}
+    with LatticeTable(ragged, A, dtype) as t:
+        info = B.spline_table_info(t.h)
+        assert np.allclose(np.array(info["lattice"]).reshape(3, 3), A)
+        for tile in [None] + list(_tiles(dtype)):
+            for kind in ("v", "vgl", "vgh"):
+                gpu, raw = run_gpu(B, t.h, kind, pos, 300, ldo=301, tile=tile)
+                assert_canary(raw, 300)
+                assert_close(kind, gpu, refs[kind], label=f"{cell} {dtype} {tile} {kind}")
+
+
+def test_diagonal_lattice_matches_box_bit_for_bit():
+    coef = synth.coef_table(6, 8, 7, 130, stream=83)
+    box = (1.3, 0.8, 2.1)
+    pos = synth.positions(200, stream=84) * 3 - 1
+    with LatticeTable(coef, np.diag(box)) as a:
+        hb = B.spline_table_create(6, 8, 7, 130, coef, "f32", box)
+        try:
+            for kind in ("v", "vgl", "vgh"):
+                _, ra = run_gpu(B, a.h, kind, pos, 130)
+                _, rb = run_gpu(B, hb, kind, pos, 130)
+                for k in ra:
+                    assert np.array_equal(ra[k], rb[k]), (kind, k)
+        finally:
+            B.spline_table_destroy(hb)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_lattice_order_changes_no_result(dtype):
+    """The cell-ordering pre-pass bins skewed cells in grid coordinates; the
+    outputs stay bit-identical to input order."""
+    coef = synth.coef_table(12, 12, 10, 260, stream=85)
+    pos = cell_positions(9000, HEX, stream=86, lo=-0.5, hi=1.5)
+    with LatticeTable(coef, HEX, dtype) as t:
+        outs = []
+        for order in (0, 1, 2):
+            _, raw = run_gpu(B, t.h, "vgh", pos, 260, tile=(2, 2, 2, 0, order))
+            outs.append(raw)
+        for o in outs[1:]:
+            for k in o:
+                assert np.array_equal(o[k], outs[0][k]), k
+        ref = oracle.evaluate_lattice("vgh", dequantized(coef, dtype), pos[:, :300], HEX)
+        got = {k: a[:300].astype(np.float64) for k, a in outs[-1].items()}
+        assert_close("vgh", got, ref, label=f"ordered lattice {dtype}")
+
+
+@pytest.mark.parametrize("kind", ["v", "vgl", "vgh"])
+def test_lattice_ratio(kind):
+    """Fused ratio on a skewed cell against the host contraction of the
+    oracle's lattice outputs with the same ainv rows."""
+    coef = synth.coef_table(9, 8, 11, 400, stream=87)
+    npos, ld = 150, 404
+    pos = cell_positions(npos, TRICLINIC, stream=88)
+    rng = np.random.default_rng(89)
+    ainv = rng.standard_normal((npos, ld)).astype(np.float32)
+    full = oracle.evaluate_lattice(kind, coef.astype(np.float64), pos, TRICLINIC)
+    comps = [full["v"]]
+    if kind != "v":
+        comps += [full["g"][:, c] for c in range(3)]
+    if kind == "vgl":
+        comps.append(full["l"])
+    if kind == "vgh":
+        comps += [full["h"][:, c] for c in range(6)]
+    a = ainv[:, :400].astype(np.float64)
+    ref = np.stack([(x * a).sum(axis=1) for x in comps], axis=1)
+    scale = np.array([np.abs(x * a).sum(axis=1).max() for x in comps])
+    dev = torch.device("cuda")
+    with LatticeTable(coef, TRICLINIC) as t:
+        pd = torch.from_numpy(pos).to(dev)
+        ad = torch.from_numpy(ainv).to(dev)
+        for tile in (None, (4, 4, 1, 0, 0), (2, 8, 1, 13, 0)):
+            out = torch.full((npos, ref.shape[1]), 7.0, dtype=torch.float64, device=dev)
+            B.spline_eval_ratio(t.h, kind, npos, pd, ad, ld, out, tile=tile)
+            torch.cuda.synchronize()
+            err = np.abs(out.cpu().numpy() - ref).max(axis=0) / scale
+            assert np.all(err <= 1e-5), (tile, err)
+
+
+@pytest.mark.parametrize("kind", ["vgl", "vgh"])
+def test_batch_plan_mixes_box_and_lattice_tables(kind):
+    shapes = [(6, 6, 6, 64), (7, 5, 9, 200), (8, 8, 8, 300)]
+    cells = [np.diag((1.2, 1.0, 0.9)), HEX, TRICLINIC]
+    npos = [40, 130, 77]
+    coefs = [synth.coef_table(*s, stream=90 + 2 * i) for i, s in enumerate(shapes)]
+    handles = [B.spline_table_create_lattice(*s, c, A) for s, c, A in zip(shapes, coefs, cells)]
+    dev = torch.device("cuda")
+    try:
+        pos = [cell_positions(n, A, stream=91 + 2 * i) for i, (n, A) in enumerate(zip(npos, cells))]
+        pd = [torch.from_numpy(p).to(dev) for p in pos]
+        ldo = [s[3] + 1 for s in shapes]
+        outs = []
+        for n, l in zip(npos, ldo):
+            o = {"v": torch.full((n, l), 12345.0, device=dev),
+                 "g": torch.full((n, 3, l), 12345.0, device=dev)}
+            o["l" if kind == "vgl" else "h"] = torch.full(
+                (n, l) if kind == "vgl" else (n, 6, l), 12345.0, device=dev)
+            outs.append(o)
+        lhk = "l" if kind == "vgl" else "h"
+        for tile in (None, (2, 2, 1, 64, 1)):
+            plan = B.spline_batch_plan_create(handles, npos, kind, pd, [o["v"] for o in outs],
+                                              [o["g"] for o in outs], [o[lhk] for o in outs],
+                                              ldo, tile=tile)
+            for rep in range(2):
+                for o in outs:
+                    for t in o.values():
+                        t[..., :-1].fill_(float(rep))
+                torch.cuda.synchronize()
+                B.spline_batch_execute(plan)
+                torch.cuda.synchronize()
+                for i in range(3):
+                    raw = {k: t.cpu().numpy() for k, t in outs[i].items()}
+                    assert_canary(raw, shapes[i][3])
+                    got = {k: a[..., :shapes[i][3]].astype(np.float64) for k, a in raw.items()}
+                    ref = oracle.evaluate_lattice(kind, coefs[i], pos[i], cells[i])
+                    assert_close(kind, got, ref, label=f"plan {tile} rep {rep} table {i}")
+            B.spline_batch_plan_destroy(plan)
+    finally:
+        for h in handles:
+            B.spline_table_destroy(h)
+
+
+def test_lattice_paper_scale_sampled():
+    """48^3 grid, 2048 splines on a hexagonal cell, 512 positions in one
+    launch; 64 sampled positions checked against the oracle."""
+    coef = synth.coef_table(48, 48, 48, 2048, stream=synth.table_stream(1))
+    pos = cell_positions(512, HEX, stream=93, lo=0.0, hi=1.0)
+    with LatticeTable(coef, HEX) as t:
+        gpu, _ = run_gpu(B, t.h, "vgh", pos, 2048, canary=False)
+    idx = np.sort(np.random.default_rng(94).choice(512, 64, replace=False))
+    ref = oracle.evaluate_lattice("vgh", coef, pos[:, idx], HEX)
+    got = {k: a[idx] for k, a in gpu.items()}
+    assert_close("vgh", got, ref, label="hex 48^3 N2048")

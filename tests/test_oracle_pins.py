@@ -422,3 +422,142 @@ MUTANTS += [
     ("for (int64_t n = 0; n < ncoef; ++n) sum += x[n] * a[n];",
      "for (int64_t n = 0; n < ncoef; ++n) sum += x[n] * a[ncoef - 1 - n];"),  # ainv reversed
 ]
+
+
+# ------------------------------------------------------------ general cells
+HEX = np.array([[1.0, 0.0, 0.0], [-0.5, np.sqrt(3) / 2, 0.0], [0.0, 0.0, 1.6]])
+TRICLINIC = np.array([[1.1, 0.1, -0.2], [0.3, 0.9, 0.15], [-0.25, 0.2, 1.3]])
+
+
+def _rotation(rng):
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def check_lattice_diagonal_is_box(orc):
+    rng = np.random.default_rng(21)
+    tab = rng.uniform(-1, 1, (5, 4, 6, 3))
+    box = (1.3, 0.7, 2.1)
+    pos = (rng.random((3, 30)) * 3 - 1) * np.array(box)[:, None]
+    a = orc.evaluate_lattice("vgh", tab, pos, np.diag(box))
+    b = orc.evaluate("vgh", tab, pos, box=box)
+    for k in ("v", "g", "h"):
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-10 * np.abs(b[k]).max())
+    al = orc.evaluate_lattice("vgl", tab, pos, np.diag(box))
+    bl = orc.evaluate("vgl", tab, pos, box=box)
+    np.testing.assert_allclose(al["l"], bl["l"], rtol=1e-12, atol=1e-10 * np.abs(bl["l"]).max())
+
+
+def check_lattice_rotation_covariance(orc):
+    """Rotating the cell and the positions together leaves V unchanged and
+    rotates G (g' = g R) and H (H' = R^T H R), row-vector convention."""
+    rng = np.random.default_rng(22)
+    tab = rng.uniform(-1, 1, (4, 5, 3, 2))
+    R = _rotation(rng)
+    pos = rng.random((3, 25)) * 2 - 0.5
+    a = orc.evaluate_lattice("vgh", tab, pos, TRICLINIC)
+    b = orc.evaluate_lattice("vgh", tab, (pos.T @ R).T, TRICLINIC @ R)
+    np.testing.assert_allclose(b["v"], a["v"], atol=1e-12)
+    gr = np.einsum("pan,ab->pbn", a["g"], R)
+    np.testing.assert_allclose(b["g"], gr, atol=1e-10 * np.abs(gr).max())
+    idx = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    H = np.zeros(a["h"].shape[:1] + (3, 3) + a["h"].shape[2:])
+    for k, (i, j) in enumerate(idx):
+        H[:, i, j] = a["h"][:, k]
+        H[:, j, i] = a["h"][:, k]
+    Hr = np.einsum("ai,pabn,bj->pijn", R, H, R)
+    want = np.stack([Hr[:, i, j] for i, j in idx], axis=1)
+    np.testing.assert_allclose(b["h"], want, atol=1e-9 * np.abs(want).max())
+    lb = orc.evaluate_lattice("vgl", tab, (pos.T @ R).T, TRICLINIC @ R)["l"]
+    np.testing.assert_allclose(lb, Hr[:, 0, 0] + Hr[:, 1, 1] + Hr[:, 2, 2],
+                               atol=1e-9 * np.abs(want).max())
+
+
+def check_lattice_polynomials(orc):
+    """Padded tables holding f(p-1) reproduce u_d and u_d^2 - 1/3 -> u_d^2
+    exactly in grid coordinates u = n (r A^-1): G = M[d] and G = 2 u_d M[d],
+    H = 0 and H = 2 M[d]^T M[d], for every cell axis d."""
+    dims = (5, 6, 4)
+    ntot = [n + 3 for n in dims]
+    cols = []
+    for d in range(3):
+        m = np.arange(ntot[d], dtype=np.float64) - 1
+        for f in (m, m * m - 1.0 / 3.0):
+            shape = [1, 1, 1]
+            shape[d] = ntot[d]
+            cols.append(np.broadcast_to(f.reshape(shape), ntot))
+    tab = np.stack(cols, axis=-1)
+    A = HEX
+    M = np.array(dims)[:, None] * np.linalg.inv(A).T      # M[d][a] = n_d inv(A)[a][d]
+    rng = np.random.default_rng(23)
+    s = rng.random((25, 3)) * 0.999
+    pos = (s @ A).T                                        # inside the cell
+    out = orc.evaluate_lattice("vgh", tab, pos, A, padded=True)
+    u = (M @ pos)                                          # [3][npos]
+    idx = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    for d in range(3):
+        lin, quad = 2 * d, 2 * d + 1
+        np.testing.assert_allclose(out["v"][:, lin], u[d], atol=1e-11)
+        np.testing.assert_allclose(out["v"][:, quad], u[d] ** 2, atol=1e-10)
+        for a in range(3):
+            np.testing.assert_allclose(out["g"][:, a, lin], M[d, a], atol=1e-11)
+            np.testing.assert_allclose(out["g"][:, a, quad], 2 * u[d] * M[d, a], atol=1e-9)
+        for k, (a, b) in enumerate(idx):
+            np.testing.assert_allclose(out["h"][:, k, lin], 0.0, atol=1e-9)
+            np.testing.assert_allclose(out["h"][:, k, quad], 2 * M[d, a] * M[d, b], atol=1e-8)
+
+
+def check_lattice_fd_and_periodicity(orc):
+    rng = np.random.default_rng(24)
+    dims = (4, 5, 6)
+    tab = rng.uniform(-1, 1, dims + (3,))
+    A = TRICLINIC
+    M = np.array(dims)[:, None] * np.linalg.inv(A).T
+    # interior points of random cells (away from faces in grid coordinates)
+    cells = np.stack([rng.integers(0, n, 12) for n in dims])
+    u = cells + 0.1 + 0.8 * rng.random((3, 12))
+    pos = np.linalg.solve(M, u)
+    base = orc.evaluate_lattice("vgh", tab, pos, A)
+    hstep = 1e-5
+    idx = {(0, 0): 0, (0, 1): 1, (0, 2): 2, (1, 1): 3, (1, 2): 4, (2, 2): 5}
+    for a in range(3):
+        pp, pm = pos.copy(), pos.copy()
+        pp[a] += hstep
+        pm[a] -= hstep
+        op = orc.evaluate_lattice("vgh", tab, pp, A)
+        om = orc.evaluate_lattice("vgh", tab, pm, A)
+        gs = np.abs(base["g"]).max()
+        np.testing.assert_allclose((op["v"] - om["v"]) / (2 * hstep), base["g"][:, a],
+                                   atol=1e-6 * gs)
+        for b in range(3):
+            hs = np.abs(base["h"]).max()
+            np.testing.assert_allclose((op["g"][:, b] - om["g"][:, b]) / (2 * hstep),
+                                       base["h"][:, idx[tuple(sorted((a, b)))]], atol=1e-6 * hs)
+    for k in ((1, 0, 0), (0, -2, 0), (3, 1, -1)):
+        shifted = pos + (np.array(k) @ A)[:, None]
+        o = orc.evaluate_lattice("vgh", tab, shifted, A)
+        for key in ("v", "g", "h"):
+            np.testing.assert_allclose(o[key], base[key], atol=1e-9 * np.abs(base[key]).max())
+
+
+LATTICE_CHECKS = [check_lattice_diagonal_is_box, check_lattice_rotation_covariance,
+                  check_lattice_polynomials, check_lattice_fd_and_periodicity]
+
+
+@pytest.mark.parametrize("check", LATTICE_CHECKS, ids=[c.__name__ for c in LATTICE_CHECKS])
+def test_lattice_pin(orc, check):
+    check(orc)
+
+
+ALL_CHECKS.extend(LATTICE_CHECKS)
+MUTANTS += [
+    ("for (int a = 0; a < 3; ++a) M[d][a] = dims[d] * ainv[3 * a + d];",
+     "for (int a = 0; a < 3; ++a) M[d][a] = dims[d] * ainv[3 * d + a];"),  # transposed inverse
+    ("for (int d = 0; d < 3; ++d) s += M[d][a] * G[d];",
+     "for (int d = 0; d < 3; ++d) s += M[a][d] * G[d];"),  # gradient transform transposed
+    ("for (int e = 0; e < 3; ++e) s += M[d][a] * M[e][b] * H[d][e];",
+     "for (int e = 0; e < 3; ++e) s += M[d][a] * M[e][a] * H[d][e];"),  # wrong Hessian index
+]
