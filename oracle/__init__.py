@@ -65,6 +65,9 @@ def _bind(path: str):
                                         ctypes.c_int, dp, ctypes.c_int64, dp, dp, dp, dp, dp,
                                         ctypes.c_int64]
     lib.oracle_eval_lattice.restype = ctypes.c_int
+    lib.oracle_fit_interpolating.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int64, dp, dp]
+    lib.oracle_fit_interpolating.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
     return lib
 
@@ -101,6 +104,9 @@ class Oracle:
 
     def evaluate_lattice(self, kind, coef, pos, lattice, padded=False):
         return evaluate_lattice(kind, coef, pos, lattice, padded, _lib_=self._l())
+
+    def fit_interpolating(self, values):
+        return fit_interpolating(values, _lib_=self._l())
 
 
 def _dp(a):
@@ -260,4 +266,16 @@ def evaluate_lattice(kind, coef: np.ndarray, pos: np.ndarray, lattice, padded: b
         out["l"] = l
     if h is not None:
         out["h"] = h
+    return out
+
+
+def fit_interpolating(values: np.ndarray, _lib_=None) -> np.ndarray:
+    """Periodic coefficients [nx][ny][nz][N] whose spline equals ``values``
+    (same shape) at the grid points."""
+    lib = _lib_ or _load()
+    values = np.ascontiguousarray(values, dtype=np.float64)
+    nx, ny, nz, n = values.shape
+    out = np.empty_like(values)
+    if lib.oracle_fit_interpolating(nx, ny, nz, n, _dp(values), _dp(out)) != 0:
+        raise ValueError("oracle_fit_interpolating rejected its arguments")
     return out

@@ -421,3 +421,105 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Interpolating coefficients (paper, "QMC and B-spline-based SPOs": the
+ * coefficients are the orbitals' interpolation tables).  Reading: the
+ * periodic spline must take the given value at every grid point.  At a grid
+ * point the fraction is 0 and the weights are B(1), B(0), B(-1), B(-2) =
+ * 1/6, 2/3, 1/6, 0, so along one axis of n points the condition is the
+ * circulant system
+ *   (1/6) c[(i-1) mod n] + (4/6) c[i] + (1/6) c[(i+1) mod n] = f[i],
+ * and in 3-D the Kronecker product of the three axis systems.  It is solved
+ * here one axis at a time with the explicit inverse of each axis matrix
+ * (Gauss-Jordan with partial pivoting), applied to every line. */
+static int invert_n(int n, const double* a_in, double* inv)
+{
+    double* a = (double*)malloc(sizeof(double) * (size_t)n * 2 * n);
+    if (!a) return -1;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < 2 * n; ++j)
+            a[i * 2 * n + j] = j < n ? a_in[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(a[r * 2 * n + c]) > fabs(a[piv * 2 * n + c])) piv = r;
+        if (a[piv * 2 * n + c] == 0.0) {
+            free(a);
+            return -1;
+        }
+        if (piv != c)
+            for (int j = 0; j < 2 * n; ++j) {
+                double t = a[c * 2 * n + j];
+                a[c * 2 * n + j] = a[piv * 2 * n + j];
+                a[piv * 2 * n + j] = t;
+            }
+        double p = a[c * 2 * n + c];
+        for (int j = 0; j < 2 * n; ++j) a[c * 2 * n + j] /= p;
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            double f = a[r * 2 * n + c];
+            for (int j = 0; j < 2 * n; ++j) a[r * 2 * n + j] -= f * a[c * 2 * n + j];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) inv[i * n + j] = a[i * 2 * n + n + j];
+    free(a);
+    return 0;
+}
+
+int oracle_fit_interpolating(int nx, int ny, int nz, int64_t ncoef, const double* values,
+                             double* coefs)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0 || ncoef <= 0 || !values || !coefs) return -1;
+    const int dims[3] = {nx, ny, nz};
+    const int64_t total = (int64_t)nx * ny * nz * ncoef;
+    double* cur = (double*)malloc(sizeof(double) * (size_t)total);
+    double* nxt = (double*)malloc(sizeof(double) * (size_t)total);
+    if (!cur || !nxt) {
+        free(cur);
+        free(nxt);
+        return -1;
+    }
+    memcpy(cur, values, sizeof(double) * (size_t)total);
+    int rc = 0;
+    for (int d = 0; d < 3 && rc == 0; ++d) {
+        const int n = dims[d];
+        double* A = (double*)calloc((size_t)n * n, sizeof(double));
+        double* Ainv = (double*)malloc(sizeof(double) * (size_t)n * n);
+        if (!A || !Ainv) rc = -1;
+        if (rc == 0) {
+            /* the axis matrix: value at grid point i of the periodic spline */
+            for (int i = 0; i < n; ++i) {
+                A[i * n + (i - 1 + n) % n] += 1.0 / 6.0;
+                A[i * n + i] += 4.0 / 6.0;
+                A[i * n + (i + 1) % n] += 1.0 / 6.0;
+            }
+            rc = invert_n(n, A, Ainv);
+        }
+        if (rc == 0) {
+            /* element (i along axis d, rest) sits at outer*n*inner + i*inner + r */
+            int64_t inner = ncoef;
+            for (int e = d + 1; e < 3; ++e) inner *= dims[e];
+            const int64_t outer = total / (inner * n);
+#pragma omp parallel for collapse(2) schedule(static)
+            for (int64_t o = 0; o < outer; ++o)
+                for (int64_t r = 0; r < inner; ++r) {
+                    const int64_t base = o * n * inner + r;
+                    for (int i = 0; i < n; ++i) {
+                        double s = 0.0;
+                        for (int j = 0; j < n; ++j) s += Ainv[i * n + j] * cur[base + j * inner];
+                        nxt[base + i * inner] = s;
+                    }
+                }
+            double* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        free(A);
+        free(Ainv);
+    }
+    if (rc == 0) memcpy(coefs, cur, sizeof(double) * (size_t)total);
+    free(cur);
+    free(nxt);
+    return rc;
+}

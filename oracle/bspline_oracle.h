@@ -86,6 +86,15 @@ int oracle_eval_lattice(int kind, int nx, int ny, int nz, int64_t ncoef,
                         const double lattice[9], int64_t npos, const double* pos,
                         double* v, double* g, double* l, double* h, int64_t ldo);
 
+/* Interpolating coefficients: the unpadded periodic coefficients c
+ * [nx][ny][nz][ncoef] whose spline takes the value values[i][j][k][n] at
+ * grid point (i, j, k) (grid units; any cell).  Solves the circulant
+ * tridiagonal system (c[i-1] + 4 c[i] + c[i+1]) / 6 = f[i] along each axis
+ * with a dense inverse.  values and coefs may not overlap.  Returns 0, or
+ * -1 on bad arguments.                                                     */
+int oracle_fit_interpolating(int nx, int ny, int nz, int64_t ncoef, const double* values,
+                             double* coefs);
+
 /* Number of OpenMP threads an oracle_eval call uses. */
 int oracle_num_threads(void);
 

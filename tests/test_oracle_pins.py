@@ -561,3 +561,73 @@ MUTANTS += [
     ("for (int e = 0; e < 3; ++e) s += M[d][a] * M[e][b] * H[d][e];",
      "for (int e = 0; e < 3; ++e) s += M[d][a] * M[e][a] * H[d][e];"),  # wrong Hessian index
 ]
+
+
+# ----------------------------------------------- interpolating coefficients
+def _grid_positions(dims, box):
+    axes = [np.arange(n) * (L / n) for n, L in zip(dims, box)]
+    g = np.meshgrid(*axes, indexing="ij")
+    return np.stack([a.ravel() for a in g])
+
+
+def check_fit_interpolates(orc):
+    """The fitted spline takes the given value at every grid point, also on
+    axes of 1, 2 and 3 points."""
+    rng = np.random.default_rng(31)
+    for dims in ((5, 4, 6), (1, 3, 2), (2, 7, 1)):
+        f = rng.uniform(-1, 1, dims + (3,))
+        box = (1.3, 0.7, 2.1)
+        c = orc.fit_interpolating(f)
+        v = orc.evaluate("v", c, _grid_positions(dims, box), box=box)["v"]
+        np.testing.assert_allclose(v, f.reshape(-1, 3), atol=1e-12)
+
+
+def check_fit_fourier_modes(orc):
+    """A periodic Fourier mode is an eigenvector of every axis system: values
+    prod_d cos(2 pi k_d i_d / n_d + phi_d) give coefficients equal to the
+    values times prod_d 3 / (2 + cos(2 pi k_d / n_d))."""
+    dims = (6, 5, 8)
+    idx = np.meshgrid(*[np.arange(n) for n in dims], indexing="ij")
+    modes = [((0, 0, 0), (0.0, 0.0, 0.0)), ((1, 2, 3), (0.3, -1.1, 0.0)),
+             ((3, 1, 4), (0.0, 0.5, 2.0)), ((2, 0, 1), (1.0, 0.0, -0.7))]
+    f = np.zeros(dims + (len(modes),))
+    want = np.zeros_like(f)
+    for m, (k, ph) in enumerate(modes):
+        val, fac = np.ones(dims), 1.0
+        for d in range(3):
+            th = 2 * np.pi * k[d] / dims[d]
+            val = val * np.cos(th * idx[d] + ph[d])
+            fac *= 3.0 / (2.0 + np.cos(th))
+        f[..., m] = val
+        want[..., m] = val * fac
+    np.testing.assert_allclose(orc.fit_interpolating(f), want, atol=1e-12)
+
+
+def check_fit_recovers_coefficients(orc):
+    """Sampling a known spline at its grid points (brute force, no cell
+    logic) and fitting returns its coefficients."""
+    rng = np.random.default_rng(32)
+    dims = (4, 3, 5)
+    c0 = rng.uniform(-1, 1, dims + (2,))
+    box = (1.0, 1.0, 1.0)
+    f = orc.evaluate_bruteforce(c0, _grid_positions(dims, box), box=box)["v"]
+    c = orc.fit_interpolating(f.reshape(dims + (2,)))
+    np.testing.assert_allclose(c, c0, atol=1e-11)
+
+
+FIT_CHECKS = [check_fit_interpolates, check_fit_fourier_modes, check_fit_recovers_coefficients]
+
+
+@pytest.mark.parametrize("check", FIT_CHECKS, ids=[c.__name__ for c in FIT_CHECKS])
+def test_fit_pin(orc, check):
+    check(orc)
+
+
+ALL_CHECKS.extend(FIT_CHECKS)
+MUTANTS += [
+    ("A[i * n + (i - 1 + n) % n] += 1.0 / 6.0;", "A[i * n + (i - 2 + n) % n] += 1.0 / 6.0;"),
+    ("A[i * n + i] += 4.0 / 6.0;", "A[i * n + i] += 4.0;"),  # unnormalised diagonal
+    ("A[i * n + (i + 1) % n] += 1.0 / 6.0;",
+     "if (i + 1 < n) A[i * n + i + 1] += 1.0 / 6.0;"),  # no periodic wrap
+    ("const int n = dims[d];\n        double* A", "const int n = dims[2 - d];\n        double* A"),
+]
