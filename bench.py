@@ -38,6 +38,8 @@ NPOS = 512
 NBATCH = 16
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_eval_vgh_f32_48cubed_N2048_512pos.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1611_02665_amd", "csrc", "eval_kernels.hip")
+# Tile wisdom for gfx950, written by the autotuner (python bench.py --retune)
+WISDOM_FILE = os.path.join(ROOT, "paper_1611_02665_amd", "wisdom_gfx950.txt")
 
 
 def log(*a):
@@ -49,9 +51,9 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(per_launch_alg_bytes):
+def read_traffic(per_launch_alg_bytes, tile):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source with the same tile (else None)."""
     if not os.path.exists(PMC_FILE):
         return None
     vals = {}
@@ -62,10 +64,26 @@ def read_traffic(per_launch_alg_bytes):
         vals[k.strip()] = v.strip()
     if vals.get("kernel_sha256_16") != kernel_hash():
         return None
+    if vals.get("tile") != ",".join(str(x) for x in tile.as_tuple()):
+        return None
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def wisdom_holds(torch, kind, npos):
+    """Whether the wisdom file has an entry for the headline table shape on
+    this device's architecture (keys: single|arch|dtype|kind|N|grid|p<pow2>)."""
+    if not os.path.exists(WISDOM_FILE):
+        return False
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    bucket = 1
+    while bucket < npos:
+        bucket <<= 1
+    key = f"single|{arch}|f32|{kind}|N{NSPL}|{GRID[0]}x{GRID[1]}x{GRID[2]}|p{bucket}"
+    with open(WISDOM_FILE) as f:
+        return any(line.split()[:1] == [key] for line in f)
 
 
 def timed(torch, fn, steps, warmup):
@@ -99,7 +117,9 @@ def main(argv=None):
     ap.add_argument("--profile", action="store_true", help="headline kernel only")
     ap.add_argument("--copy-probe", action="store_true", help="only a 1 GiB device copy")
     ap.add_argument("--tile", default=None,
-                    help="profiling: fixed tile vw,wx,wy,grid,order instead of autotuning")
+                    help="profiling: fixed tile vw,wx,wy,grid,order instead of the wisdom")
+    ap.add_argument("--retune", action="store_true",
+                    help="autotune the headline tile and append it to the wisdom file")
     ap.add_argument("--npos", type=int, default=NPOS,
                     help="profiling: positions per batch (the benchmark itself uses 512)")
     ap.add_argument("--sweep", action="store_true",
@@ -150,11 +170,19 @@ def main(argv=None):
     pp = [b.data_ptr() for b in batches]
     vp, gp, hp, lp = v.data_ptr(), g.data_ptr(), h.data_ptr(), l.data_ptr()
     if args.tile:
-        tile = B.bspl_tile(*[int(x) for x in args.tile.split(",")])
+        tile, tile_source = B.bspl_tile(*[int(x) for x in args.tile.split(",")]), "fixed"
+    elif args.retune:
+        tile, tile_source = B.spline_autotune(t32, "vgh", npos, WISDOM_FILE), "autotune"
     else:
-        # the autotuner picks the work decomposition (kept in the in-process wisdom)
-        tile = B.spline_autotune(t32, "vgh", npos)
-    log(f"[bench] table ready, tile {tile}")
+        # the tile the autotuner chose for this shape on this architecture,
+        # else a live sweep (recorded in the in-process wisdom)
+        tile_source = "wisdom" if wisdom_holds(torch, "vgh", npos) else "autotune"
+        if tile_source == "wisdom":
+            B.spline_wisdom_load(WISDOM_FILE)
+            tile = B.spline_tile_select(t32, "vgh", npos)
+        else:
+            tile = B.spline_autotune(t32, "vgh", npos)
+    log(f"[bench] table ready, tile {tile} ({tile_source})")
     tref = B.ctypes.byref(tile)
 
     def vgh_step(i):
@@ -173,7 +201,7 @@ def main(argv=None):
         B.spline_table_destroy(t32)
         return 0
 
-    traffic = read_traffic(alg_bytes)
+    traffic = read_traffic(alg_bytes, tile)
     line = {
         "metric": METRIC,
         "value": value,
@@ -191,7 +219,7 @@ def main(argv=None):
             "workload": "eval_vgh, 48^3 periodic grid (51^3 padded) x N=2048 FP32 table "
                         "(1.09 GB), 512 uniform positions per batch, 16 batches cycled",
             "grid": list(GRID), "n_splines": NSPL, "npos": NPOS, "kernel": "eval_vgh",
-            "table_dtype": "f32", "tile": list(tile.as_tuple()),
+            "table_dtype": "f32", "tile": list(tile.as_tuple()), "tile_source": tile_source,
         },
         "hbm_gbs": achieved,
         "roofline": {
@@ -213,6 +241,22 @@ def main(argv=None):
         extra["vgl"] = {"evals_per_s": evals / (ms_l * 1e-3), "us_per_launch": ms_l * 1e3,
                         "hbm_gbs": A.batch_bytes("vgl", "f32", NPOS, NSPL) / (ms_l * 1e-3) / 1e9,
                         "tile": list(tile_l.as_tuple())}
+        # the same coefficients on a hexagonal cell (a general lattice: grid
+        # coordinates u = M r, derivatives carried to Cartesian ones)
+        hexcell = [[1.0, 0.0, 0.0], [-0.5, 0.75 ** 0.5, 0.0], [0.0, 0.0, 1.6]]
+        thex = B.spline_table_create_lattice(*GRID, NSPL, coef, hexcell)
+        extra["lattice_hex"] = {}
+        for kind, ob in (("vgh", hp), ("vgl", lp)):
+            ht = B.spline_autotune(thex, kind, NPOS)
+            href = B.ctypes.byref(ht)
+            ms_h = timed(torch, lambda i: B._check(B.lib.spline_eval(
+                thex, B.KINDS[kind], NPOS, pp[i % nbatch], vp, gp, ob, ldo, href, stream),
+                "spline_eval"), max(100, steps // 2), warmup)
+            extra["lattice_hex"][kind] = {
+                "evals_per_s": evals / (ms_h * 1e-3), "us_per_launch": ms_h * 1e3,
+                "hbm_gbs": A.batch_bytes(kind, "f32", NPOS, NSPL) / (ms_h * 1e-3) / 1e9,
+                "tile": list(ht.as_tuple())}
+        B.spline_table_destroy(thex)
         # fused determinant ratios on the same workload: 64*4 table bytes +
         # 4 bytes of inverse-matrix row per eval, no N-wide output rows
         ainv = torch.randn(NPOS, NSPL, device=dev)

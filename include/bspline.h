@@ -62,6 +62,9 @@ typedef enum { BSPL_V = 0, BSPL_VGL = 1, BSPL_VGH = 2 } bspl_kind;
 /* spline_table_create flags */
 #define BSPL_COEFS_PADDED 0x1u /* coefs are [nx+3][ny+3][nz+3][N], used as-is */
 #define BSPL_COEFS_DEVICE 0x2u /* coefs is a device pointer (else host)     */
+#define BSPL_COEFS_GRID_VALUES 0x4u /* coefs are orbital values at the grid
+                                       points; the table gets the interpolating
+                                       coefficients (spline_fit_interpolating) */
 
 typedef struct bspl_table bspl_table;
 typedef struct bspl_plan bspl_plan;
@@ -153,6 +156,23 @@ bspl_status spline_table_create_lattice(bspl_table** out, int nx, int ny, int nz
                                         int64_t n_splines, const float* coefs,
                                         bspl_dtype dtype, const double lattice[9],
                                         unsigned flags, void* stream);
+
+/* Interpolating coefficients (paper, "QMC and B-spline-based SPOs": the
+ * coefficients are the orbitals' interpolation tables).  values and coefs
+ * are device arrays [nx][ny][nz][n_splines], n fastest: values[i][j][k][n]
+ * is orbital n at grid point (i, j, k); on return coefs holds the periodic
+ * coefficients whose spline takes exactly those values at the grid points,
+ * i.e. the solution of (c[i-1] + 4 c[i] + c[i+1]) / 6 = f[i] (indices mod
+ * n) along each axis.  The solve does not depend on the cell shape, so the
+ * result serves box and lattice tables alike.  coefs == values (in place)
+ * is allowed; any other overlap is undefined.  FP64 recursions, FP32
+ * storage between the three axis passes.  Asynchronous on the stream.
+ * Errors: EINVAL (sizes <= 0, NULL pointers), EUNSUPPORTED (byte count
+ * overflow), EDEVICE.  The same fit runs inside spline_table_create and
+ * spline_table_create_lattice when flags hold BSPL_COEFS_GRID_VALUES
+ * (host or device values; not with BSPL_COEFS_PADDED).                   */
+bspl_status spline_fit_interpolating(int nx, int ny, int nz, int64_t n_splines,
+                                     const float* values, float* coefs, void* stream);
 
 /* Free a table.  NULL is accepted.  No evaluation may still be in flight on
  * it (hipFree semantics). */

@@ -29,6 +29,7 @@ BSPL_F32, BSPL_F16, BSPL_BF16 = 0, 1, 2
 BSPL_V, BSPL_VGL, BSPL_VGH = 0, 1, 2
 BSPL_COEFS_PADDED = 0x1
 BSPL_COEFS_DEVICE = 0x2
+BSPL_COEFS_GRID_VALUES = 0x4
 MAX_TABLES = 16
 
 DTYPES = {"f32": BSPL_F32, "f16": BSPL_F16, "bf16": BSPL_BF16}
@@ -75,6 +76,7 @@ _SIGS = {
     "spline_layout_query": (_int, [_int, _int, _int, _i64, _int, _P(bspl_table_info)]),
     "spline_table_create": (_int, [_P(_vp), _int, _int, _int, _i64, _vp, _int,
                                    _P(ctypes.c_double), _u32, _vp]),
+    "spline_fit_interpolating": (_int, [_int, _int, _int, _i64, _vp, _vp, _vp]),
     "spline_table_create_lattice": (_int, [_P(_vp), _int, _int, _int, _i64, _vp, _int,
                                            _P(ctypes.c_double), _u32, _vp]),
     "spline_table_destroy": (_int, [_vp]),
@@ -181,6 +183,12 @@ def spline_table_create_lattice(nx, ny, nz, n_splines, coefs, lattice, dtype="f3
                                            _enum(dtype, DTYPES), lat, flags, _stream(stream)),
            "spline_table_create_lattice")
     return h.value
+
+
+def spline_fit_interpolating(nx, ny, nz, n_splines, values, coefs, stream=None) -> None:
+    """Device arrays [nx][ny][nz][n_splines]; coefs may be values (in place)."""
+    _check(lib.spline_fit_interpolating(nx, ny, nz, n_splines, _ptr(values), _ptr(coefs),
+                                        _stream(stream)), "spline_fit_interpolating")
 
 
 def spline_table_destroy(table) -> None:

@@ -15,7 +15,7 @@ LIB = os.path.join(PKG, "libbspline.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 SOURCES = ["table.cpp", "eval_kernels.hip", "layout_kernels.hip", "order_kernels.hip",
-           "autotune.cpp", "batch.cpp"]
+           "fit_kernels.hip", "autotune.cpp", "batch.cpp"]
 ARCH = os.environ.get("BSPL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

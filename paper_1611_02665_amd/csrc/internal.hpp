@@ -109,6 +109,11 @@ struct OrderLaunch {
 };
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o);
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s);
+
+// Interpolating coefficients: three in-place axis passes, src -> dst (src may
+// equal dst), both unpadded [nx][ny][nz][nspl] FP32 on the device.
+bspl_status launch_fit(int nx, int ny, int nz, int64_t nspl, const float* src, float* dst,
+                       hipStream_t s);
 const void* order_kernel_ptr();
 
 // Table layout kernels (layout_kernels.hip).

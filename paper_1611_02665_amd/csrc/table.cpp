@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 
 #include "internal.hpp"
@@ -204,8 +205,11 @@ bspl_status create_table(bspl_table** out, int nx, int ny, int nz, int64_t n_spl
     if (!out) return fail(BSPL_EINVAL, "out is NULL");
     *out = nullptr;
     if (!coefs) return fail(BSPL_EINVAL, "coefs is NULL");
-    if (flags & ~(BSPL_COEFS_PADDED | BSPL_COEFS_DEVICE))
+    if (flags & ~(BSPL_COEFS_PADDED | BSPL_COEFS_DEVICE | BSPL_COEFS_GRID_VALUES))
         return fail(BSPL_EINVAL, "unknown flags 0x%x", flags);
+    if ((flags & BSPL_COEFS_PADDED) && (flags & BSPL_COEFS_GRID_VALUES))
+        return fail(BSPL_EINVAL, "grid values are unpadded: BSPL_COEFS_PADDED with "
+                                 "BSPL_COEFS_GRID_VALUES");
     bspl_table_info info{};
     bspl_status st = spline_layout_query(nx, ny, nz, n_splines, dtype, &info);
     if (st != BSPL_OK) return st;
@@ -243,17 +247,29 @@ bspl_status create_table(bspl_table** out, int nx, int ny, int nz, int64_t n_spl
             return hip_fail(e, "hipMalloc(scales)");
         }
     }
+    // host coefficients are staged on the device; grid values are turned
+    // into interpolating coefficients there (in the staging buffer, or in a
+    // buffer of their own when the caller's values are on the device)
+    const bool from_host = !(flags & BSPL_COEFS_DEVICE);
+    const bool fit = (flags & BSPL_COEFS_GRID_VALUES) != 0;
     const float* d_src = coefs;
     float* staging = nullptr;
-    if (!(flags & BSPL_COEFS_DEVICE)) {
+    if (from_host || fit) {
         e = hipMalloc((void**)&staging, sizeof(float) * (size_t)src_elems);
-        if (e == hipSuccess)
+        if (e == hipSuccess && from_host)
             e = hipMemcpyAsync(staging, coefs, sizeof(float) * (size_t)src_elems,
                                hipMemcpyHostToDevice, s);
         if (e != hipSuccess) {
             if (staging) (void)hipFree(staging);
             spline_table_destroy(t);
             return hip_fail(e, "staging coefficients on the device");
+        }
+        st = fit ? launch_fit(nx, ny, nz, n_splines, from_host ? staging : coefs, staging, s)
+                 : BSPL_OK;
+        if (st != BSPL_OK) {
+            (void)hipFree(staging);
+            spline_table_destroy(t);
+            return st;
         }
         d_src = staging;
     }
@@ -297,6 +313,21 @@ bspl_status spline_table_create_lattice(bspl_table** out, int nx, int ny, int nz
         return fail(BSPL_EINVAL, "lattice is NULL");
     }
     return create_table(out, nx, ny, nz, n_splines, coefs, dtype, lattice, flags, stream);
+}
+
+bspl_status spline_fit_interpolating(int nx, int ny, int nz, int64_t n_splines,
+                                     const float* values, float* coefs, void* stream) {
+    if (nx <= 0 || ny <= 0 || nz <= 0 || n_splines <= 0)
+        return fail(BSPL_EINVAL, "sizes must be positive (%d, %d, %d, %lld)", nx, ny, nz,
+                    (long long)n_splines);
+    if (!values || !coefs) return fail(BSPL_EINVAL, "values or coefs is NULL");
+    const int64_t lim = INT64_MAX / 4;
+    int64_t total = n_splines;
+    for (int n : {nx, ny, nz}) {
+        if (total > lim / n) return fail(BSPL_EUNSUPPORTED, "grid too large");
+        total *= n;
+    }
+    return launch_fit(nx, ny, nz, n_splines, values, coefs, static_cast<hipStream_t>(stream));
 }
 
 bspl_status spline_table_destroy(bspl_table* t) {

@@ -115,6 +115,23 @@ def test_create_lattice_validates_before_touching_the_device():
     assert f(None, 1, 1, 1, 8, coefs, 0, ok, 0, None) == B.BSPL_EINVAL
 
 
+def test_fit_validates_before_touching_the_device():
+    buf = (ctypes.c_float * 8)()
+    f = B.lib.spline_fit_interpolating
+    assert f(0, 2, 2, 1, buf, buf, None) == B.BSPL_EINVAL
+    assert f(2, 2, 2, 0, buf, buf, None) == B.BSPL_EINVAL
+    assert f(2, 2, 2, 1, None, buf, None) == B.BSPL_EINVAL
+    assert f(2, 2, 2, 1, buf, None, None) == B.BSPL_EINVAL
+    assert f(1 << 30, 1 << 30, 1 << 30, 1 << 20, buf, buf, None) == B.BSPL_EUNSUPPORTED
+    # grid values are unpadded: the two flags exclude each other
+    h = ctypes.c_void_p(7)
+    assert B.lib.spline_table_create(ctypes.byref(h), 1, 1, 1, 8, buf, 0, None,
+                                     B.BSPL_COEFS_PADDED | B.BSPL_COEFS_GRID_VALUES,
+                                     None) == B.BSPL_EINVAL
+    assert h.value is None
+    assert "GRID_VALUES" in B.spline_last_error()
+
+
 def test_tile_struct_matches_header():
     text = open(HEADER).read()
     body = text[text.index("typedef struct {\n    int32_t vw;"):]
