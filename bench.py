@@ -257,6 +257,16 @@ def main(argv=None):
                 "hbm_gbs": A.batch_bytes(kind, "f32", NPOS, NSPL) / (ms_h * 1e-3) / 1e9,
                 "tile": list(ht.as_tuple())}
         B.spline_table_destroy(thex)
+        # interpolating coefficients from grid values (table set-up, once per
+        # orbital set): one HBM read and one write per element and axis
+        vals = torch.from_numpy(coef).to(dev)
+        fitted = torch.empty_like(vals)
+        ms_f = timed(torch, lambda i: B.spline_fit_interpolating(*GRID, NSPL, vals, fitted,
+                                                                 stream=stream), 10, 2)
+        fit_bytes = 3 * 8 * vals.numel()
+        extra["fit_interpolating"] = {"ms": ms_f, "alg_bytes": fit_bytes,
+                                      "hbm_gbs": fit_bytes / (ms_f * 1e-3) / 1e9}
+        del vals, fitted
         # fused determinant ratios on the same workload: 64*4 table bytes +
         # 4 bytes of inverse-matrix row per eval, no N-wide output rows
         ainv = torch.randn(NPOS, NSPL, device=dev)

@@ -71,6 +71,56 @@ __global__ void __launch_bounds__(kFitThreads) fit_axis_kernel(
     }
 }
 
+// The same two recursions with the line staged in LDS: a wavefront loads
+// its 64 lines (n x 64 floats, lane-contiguous, so conflict-free) with n
+// independent loads per lane, runs both recursions in LDS and stores each
+// coefficient once: one read and one write of HBM per element and axis
+// instead of two of each.  Used while n * 256 B fits in 64 KiB.
+constexpr int kLdsMaxN = 256;
+
+__global__ void __launch_bounds__(64) fit_axis_lds_kernel(
+    const float* src, float* dst, int n, int64_t inner, int64_t lines, double gain,
+    int start_terms) {
+    extern __shared__ float line[];  // [n][64]
+    const int lane = threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+    const bool live = t < lines;
+    const int64_t o = live ? t / inner : 0;
+    const int64_t base = live ? o * (int64_t)n * inner + (t - o * inner) : 0;
+    float* my = line + lane;
+    if (live) {
+#pragma unroll 8
+        for (int i = 0; i < n; ++i) my[i * 64] = src[base + (int64_t)i * inner];
+    }
+    // each lane touches only its own column: no barrier is needed
+    if (!live) return;
+    double pk = 1.0, y = 0.0;
+    for (int k = 0; k < start_terms; ++k) {
+        const int i = k == 0 ? 0 : n - k;
+        y = __builtin_fma(pk, (double)my[i * 64], y);
+        pk *= kPole;
+    }
+    y *= gain;
+    my[0] = (float)y;
+    for (int i = 1; i < n; ++i) {
+        y = __builtin_fma(kPole, y, (double)my[i * 64]);
+        my[i * 64] = (float)y;
+    }
+    pk = kPole;
+    double w = y;
+    for (int k = 1; k < start_terms; ++k) {
+        w = __builtin_fma(pk, (double)my[(k - 1) * 64], w);
+        pk *= kPole;
+    }
+    w *= gain;
+    const double out_scale = -6.0 * kPole;
+    dst[base + (int64_t)(n - 1) * inner] = (float)(out_scale * w);
+    for (int i = n - 2; i >= 0; --i) {
+        w = __builtin_fma(kPole, w, (double)my[i * 64]);
+        dst[base + (int64_t)i * inner] = (float)(out_scale * w);
+    }
+}
+
 }  // namespace
 
 bspl_status launch_fit(int nx, int ny, int nz, int64_t nspl, const float* src, float* dst,
@@ -86,9 +136,17 @@ bspl_status launch_fit(int nx, int ny, int nz, int64_t nspl, const float* src, f
         for (int k = 0; k < n && k < 64; ++k) pn *= kPole;  // p^n (0 to FP64 beyond 64)
         const double gain = 1.0 / (1.0 - pn);
         const int start_terms = n < kStartTerms ? n : kStartTerms;
-        const int64_t blocks = (lines + kFitThreads - 1) / kFitThreads;
-        hipLaunchKernelGGL(fit_axis_kernel, dim3((unsigned)blocks), dim3(kFitThreads), 0, s,
-                           d == 0 ? src : dst, dst, n, inner, lines, gain, start_terms);
+        const float* in = d == 0 ? src : dst;
+        if (n <= kLdsMaxN) {
+            const int64_t blocks = (lines + 63) / 64;
+            hipLaunchKernelGGL(fit_axis_lds_kernel, dim3((unsigned)blocks), dim3(64),
+                               (size_t)n * 64 * sizeof(float), s, in, dst, n, inner, lines,
+                               gain, start_terms);
+        } else {
+            const int64_t blocks = (lines + kFitThreads - 1) / kFitThreads;
+            hipLaunchKernelGGL(fit_axis_kernel, dim3((unsigned)blocks), dim3(kFitThreads), 0,
+                               s, in, dst, n, inner, lines, gain, start_terms);
+        }
         BSPL_HIP(hipGetLastError());
     }
     return BSPL_OK;

@@ -57,10 +57,12 @@ def _smooth_values(dims, n, seed):
 
 
 @pytest.mark.parametrize("shape", [(7, 9, 5, 300), (1, 2, 3, 5), (2, 1, 40, 64),
-                                   (100, 3, 2, 70), (33, 31, 32, 17), (48, 48, 60, 128)])
+                                   (100, 3, 2, 70), (33, 31, 32, 17), (48, 48, 60, 128),
+                                   (300, 2, 1, 5), (2, 3, 260, 70)])
 def test_fit_matches_oracle(shape):
     """Random values (axes of 1 and 2 points, axes shorter and longer than
-    the 32-term periodic start, ragged N)."""
+    the 32-term periodic start, ragged N; axes of 300 and 260 points take
+    the global-memory passes, shorter ones the LDS-staged passes)."""
     values = synth.coef_table(*shape, stream=101)
     ref = oracle.fit_interpolating(values.astype(np.float64))
     got = _gpu_fit(values)
