@@ -82,8 +82,8 @@ def wisdom_holds(torch, kind, npos):
     while bucket < npos:
         bucket <<= 1
     key = f"single|{arch}|f32|{kind}|N{NSPL}|{GRID[0]}x{GRID[1]}x{GRID[2]}|p{bucket}"
-    with open(WISDOM_FILE) as f:
-        return any(line.split()[:1] == [key] for line in f)
+    with open(WISDOM_FILE) as f:  # key vw wx wy grid order split [time_us]
+        return any(len(line.split()) >= 8 and line.split()[0] == key for line in f)
 
 
 def timed(torch, fn, steps, warmup):
@@ -296,6 +296,8 @@ def main(argv=None):
         log("[bench] precision extra done")
         extra["batched"] = batched_extra(torch, B, A, synth, steps, warmup)
         log("[bench] batched extra done")
+        extra["latency"] = latency_extra(torch, B, synth, t32)
+        log("[bench] latency extra done")
         extra["large"] = large_extra(torch, B, A, synth, warmup)
         log("[bench] large-table extra done")
         line["extra"] = extra
@@ -453,6 +455,47 @@ def batched_extra(torch, B, A, synth, steps, warmup):
             B.spline_table_destroy(t)
     res["f16_speedup_vs_f32"] = res["f16"]["evals_per_s"] / res["f32"]["evals_per_s"]
     return res
+
+
+def latency_extra(torch, B, synth, t32, k=64, reps=20):
+    """Latency mode: one eval_vgh of a few positions per launch, k launches
+    on distinct position sets captured in a HIP graph and replayed; time per
+    evaluation with unsplit units and with 4 wavefronts per unit."""
+    dev = torch.device("cuda")
+    out = {}
+    for npos in (1, 4, 16):
+        pos = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0),
+                                                batch=500 + b)).to(dev) for b in range(k)]
+        v = torch.empty(npos, NSPL, device=dev)
+        g = torch.empty(npos, 3, NSPL, device=dev)
+        h = torch.empty(npos, 6, NSPL, device=dev)
+        row = {}
+        for name, tile in (("unsplit", (1, 1, 1, 0, 0, 1)), ("split4", (1, 1, 1, 0, 0, 4))):
+            gs = torch.cuda.Stream()
+            gs.wait_stream(torch.cuda.current_stream())
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(gs):
+                B.spline_eval(t32, "vgh", npos, pos[0], v, g, h, NSPL, tile=tile,
+                              stream=gs.cuda_stream)
+                torch.cuda.synchronize()
+                with torch.cuda.graph(graph, stream=gs):
+                    for i in range(k):
+                        B.spline_eval(t32, "vgh", npos, pos[i], v, g, h, NSPL, tile=tile,
+                                      stream=gs.cuda_stream)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                graph.replay()
+            b.record()
+            torch.cuda.synchronize()
+            row[f"{name}_us_per_eval"] = a.elapsed_time(b) / (reps * k) * 1e3
+            del graph
+        out[f"npos{npos}"] = row
+    return out
 
 
 def large_extra(torch, B, A, synth, warmup):

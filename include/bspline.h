@@ -102,13 +102,23 @@ typedef struct {
  * positions, on the device, in stream-ordered scratch memory) so that
  * positions sharing table rows are evaluated together; order = 2 also hands
  * each of the 8 XCDs a contiguous run of the ordered blocks.  The order
- * changes no result: every output is computed the same way.              */
+ * changes no result: every output is computed the same way.
+ * split = 2 or 4 is the latency mode for a few positions (the GPU form of
+ * the paper's nested threading within one walker, section "Optimizations
+ * and Parallelization"): that many wavefronts share one (position, tile)
+ * unit, each gathering 1/split of its 16 row groups with all of them in
+ * flight, and the partial sums are added in LDS in a fixed order.  A split
+ * workgroup holds wx tiles x split wavefronts of one position (wy must be
+ * 1, grid 0, wx*split <= 8, and split*wx*n_out*vw*256 bytes of partial sums
+ * at most 64 KiB).  Results differ from split = 1 only by rounding; split
+ * = 0 means 1.  Evaluations only (not ratios or batch plans).            */
 typedef struct {
     int32_t vw;    /* splines per lane: 1, 2, 4 (F32) or 2, 4, 8 (F16/BF16) */
     int32_t wx;    /* wavefronts per workgroup along splines */
     int32_t wy;    /* wavefronts per workgroup along positions */
     int32_t grid;  /* persistent workgroups, or 0 */
     int32_t order; /* 0 input order, 1 cell-sorted, 2 cell-sorted + XCD-grouped */
+    int32_t split; /* 0 or 1; 2 or 4 wavefronts per unit (latency mode) */
 } bspl_tile;
 
 /* Human-readable name of a status code (static string). */
@@ -236,7 +246,9 @@ bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos
 bspl_status spline_autotune(const bspl_table* t, bspl_kind kind, int64_t npos,
                             const char* wisdom_path, bspl_tile* best, void* stream);
 
-/* Load wisdom entries from a file into the cache (EIO if unreadable). */
+/* Load wisdom entries from a file into the cache (EIO if unreadable).  One
+ * entry per line: "key vw wx wy grid order split [time_us]"; other lines
+ * (comments, older formats) are skipped.                                 */
 bspl_status spline_wisdom_load(const char* path);
 
 /* Write the whole wisdom cache to a file (EIO on failure). */

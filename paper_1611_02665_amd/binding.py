@@ -56,14 +56,14 @@ class bspl_table_info(ctypes.Structure):
 
 class bspl_tile(ctypes.Structure):
     _fields_ = [("vw", ctypes.c_int32), ("wx", ctypes.c_int32), ("wy", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("grid", ctypes.c_int32), ("order", ctypes.c_int32), ("split", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.vw, self.wx, self.wy, self.grid, self.order)
+        return (self.vw, self.wx, self.wy, self.grid, self.order, self.split)
 
     def __repr__(self):
         return (f"bspl_tile(vw={self.vw}, wx={self.wx}, wy={self.wy}, grid={self.grid}, "
-                f"order={self.order})")
+                f"order={self.order}, split={self.split})")
 
 
 lib = ctypes.CDLL(LIB_PATH)

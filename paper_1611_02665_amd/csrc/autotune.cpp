@@ -55,7 +55,9 @@ int64_t pow2_bucket(int64_t n) {
 bool parse_line(const char* line, std::string* key, bspl_tile* t) {
     char k[256];
     bspl_tile x{};
-    if (sscanf(line, "%255s %d %d %d %d %d", k, &x.vw, &x.wx, &x.wy, &x.grid, &x.order) != 6)
+    // key vw wx wy grid order split [time_us]
+    if (sscanf(line, "%255s %d %d %d %d %d %d", k, &x.vw, &x.wx, &x.wy, &x.grid, &x.order,
+               &x.split) != 7)
         return false;
     *key = k;
     *t = x;
@@ -102,7 +104,8 @@ void wisdom_store(const char* key, const bspl_tile& tile) {
 
 // Candidate decompositions for a table (and, for batched launches, grid
 // sizes as multiples of the compute-unit count).
-std::vector<bspl_tile> tile_candidates(int dtype, int64_t max_nsplines, bool persistent) {
+std::vector<bspl_tile> tile_candidates(int dtype, int kind, int64_t max_nsplines, int64_t npos,
+                                       bool persistent) {
     std::vector<bspl_tile> out;
     const int vws32[] = {1, 2, 4}, vws16[] = {2, 4, 8};
     const int* vws = dtype == BSPL_F32 ? vws32 : vws16;
@@ -121,8 +124,17 @@ std::vector<bspl_tile> tile_candidates(int dtype, int64_t max_nsplines, bool per
             const int ng = persistent ? 5 : 1;
             for (int gi = 0; gi < ng; ++gi)
                 for (int order = 0; order <= 2; ++order)
-                    out.push_back(bspl_tile{vw, s[0], s[1], grids[gi] * cus, order});
+                    out.push_back(bspl_tile{vw, s[0], s[1], grids[gi] * cus, order, 1});
         }
+        // latency mode (single evaluations): wx tiles x split wavefronts per
+        // position, input order
+        if (persistent || npos > kSplitMaxPositions) continue;
+        for (int split : {2, 4})
+            for (int wx : {1, 2, 4}) {
+                if (wx * split > 8 || (wx > chunks && wx > 1)) continue;
+                if (split_lds_bytes(kind, vw, wx, split) > kSplitMaxLds) continue;
+                out.push_back(bspl_tile{vw, wx, 1, 0, 0, split});
+            }
     }
     return out;
 }
@@ -196,7 +208,8 @@ static bspl_status append_wisdom(const char* path, const char* key, const bspl_t
                                  float us) {
     FILE* f = fopen(path, "a");
     if (!f) return fail(BSPL_EIO, "cannot append to wisdom file %s", path);
-    fprintf(f, "%s %d %d %d %d %d %.3f\n", key, t.vw, t.wx, t.wy, t.grid, t.order, us);
+    fprintf(f, "%s %d %d %d %d %d %d %.3f\n", key, t.vw, t.wx, t.wy, t.grid, t.order, t.split,
+            us);
     const bool ok = fclose(f) == 0;
     return ok ? BSPL_OK : fail(BSPL_EIO, "cannot write wisdom file %s", path);
 }
@@ -265,7 +278,7 @@ bspl_status spline_autotune(const bspl_table* t, bspl_kind kind, int64_t npos,
     bspl_tile bt{};
     float us = 0;
     if (st == BSPL_OK) {
-        auto cands = tile_candidates(t->info.dtype, t->info.n_splines, false);
+        auto cands = tile_candidates(t->info.dtype, kind, t->info.n_splines, npos, false);
         st = sweep(cands, s, run_single, &c, &bt, &us);
     }
     (void)hipStreamSynchronize(s);
@@ -302,8 +315,8 @@ bspl_status spline_wisdom_save(const char* path) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         for (auto& kv : cache())
-            fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.vw, kv.second.wx,
-                    kv.second.wy, kv.second.grid, kv.second.order);
+            fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.vw, kv.second.wx,
+                    kv.second.wy, kv.second.grid, kv.second.order, kv.second.split);
     }
     return fclose(f) == 0 ? BSPL_OK : fail(BSPL_EIO, "cannot write wisdom file %s", path);
 }

@@ -175,7 +175,7 @@ bspl_status autotune_plan(bspl_plan* p, hipStream_t s, bspl_tile* best, float* u
     }
     if (st == BSPL_OK) {
         std::vector<bspl_tile> cands;
-        for (const bspl_tile& t : tile_candidates(p->dtype, max_n, true))
+        for (const bspl_tile& t : tile_candidates(p->dtype, p->kind, max_n, 0, true))
             if (t.grid > 0) cands.push_back(t);  // persistent launches only
         st = sweep(cands, s, run_batch, &c, best, us);
     }
@@ -296,6 +296,10 @@ bspl_status spline_batch_plan_create(bspl_plan** out, int ntables, const bspl_ta
         if (!tile_valid(*tile, p->dtype)) {
             spline_batch_plan_destroy(p);
             return fail(BSPL_EINVAL, "tile invalid for dtype");
+        }
+        if (tile->split > 1) {
+            spline_batch_plan_destroy(p);
+            return fail(BSPL_EINVAL, "split tiles are for single evaluations only");
         }
         p->tile = *tile;
     } else {

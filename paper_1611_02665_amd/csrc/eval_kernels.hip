@@ -173,29 +173,19 @@ template <typename T, int VW> struct Depth {
     static constexpr int value = 32 / (VW * Elem<T>::bytes) < 2 ? 2 : 32 / (VW * Elem<T>::bytes);
 };
 
-// Steps 1-3 (and the scale of step 4) for one work unit: on return acc holds
-// the unit's outputs for splines [n0, n0 + VW) of lane `lane`, of which
-// `valid` (if positive) are real splines.
-// Select element i (0..8) of nine uniform values without indexing memory.
-template <typename V>
-__device__ __forceinline__ V pick9(const V (&m)[9], int i) {
-    V r = m[0];
-#pragma unroll
-    for (int k = 1; k < 9; ++k) r = i == k ? m[k] : r;
-    return r;
-}
-
 // Upper-triangle component k (xx, xy, xz, yy, yz, zz) as an index pair.
 __device__ __forceinline__ int sym_row(int k) { return k < 3 ? 0 : (k < 5 ? 1 : 2); }
 __device__ __forceinline__ int sym_col(int k) { return k < 3 ? k : (k < 5 ? k - 2 : 2); }
 
 // Coefficient of grid-space Hessian component q in Cartesian component k:
 // H_r[a][b] = sum_{d,e} M[d][a] M[e][b] H_u[d][e], with the symmetric
-// off-diagonal pairs of H_u folded together.
-__device__ __forceinline__ float hess_coef(const float (&m)[9], int k, int q) {
+// off-diagonal pairs of H_u folded together.  The per-lane indices read the
+// map straight from the descriptor (kernel-argument memory), which keeps
+// it out of private memory.
+__device__ __forceinline__ float hess_coef(const TableDesc& d, int k, int q) {
     const int a = sym_row(k), b = sym_col(k), dd = sym_row(q), e = sym_col(q);
-    float c = pick9(m, 3 * dd + a) * pick9(m, 3 * e + b);
-    if (dd != e) c = fmaf(pick9(m, 3 * e + a), pick9(m, 3 * dd + b), c);
+    float c = d.Mf[dd][a] * d.Mf[e][b];
+    if (dd != e) c = fmaf(d.Mf[e][a], d.Mf[dd][b], c);
     return c;
 }
 
@@ -205,10 +195,18 @@ template <int KIND, int LAT> struct Internal {
     static constexpr int kind = (LAT && KIND == BSPL_VGL) ? BSPL_VGH : KIND;
 };
 
-template <typename T, int VW, int KIND, int LAT, int DEPTH = Depth<T, VW>::value>
+// Steps 1-4 for one work unit: on return out holds the unit's outputs for
+// splines [n0, n0 + VW) of lane `lane`, of which `valid` (if positive) are
+// real splines.  NG < 16 evaluates only the row groups of the x-slabs
+// [islab, islab + NG/4): the partial sum that one wavefront of a split unit
+// contributes (every step after the gather is linear in the coefficients).
+template <typename T, int VW, int KIND, int LAT, int NG = 16,
+          int DEPTH = Depth<T, VW>::value>
 __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, int lane,
                                           float (&out)[Shape<KIND>::nout][VW], int& n0_out,
-                                          int& valid_out) {
+                                          int& valid_out, int islab = 0) {
+    static_assert(NG == 16 || NG == 8 || NG == 4, "whole x-slabs only");
+    static_assert(DEPTH >= 1 && DEPTH <= NG, "ring deeper than the groups");
     constexpr int EB = Elem<T>::bytes;
     constexpr int KI = Internal<KIND, LAT>::kind;  // what is accumulated
     constexpr int NOUT = Shape<KI>::nout;
@@ -259,12 +257,13 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     float ax[4], dax[4], d2ax[4], ay[4], day[4], d2ay[4], az[4], daz[4], d2az[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        ax[m] = bcast(wv, m);
+        // x weights of this unit's slabs (islab is 0 unless the unit is split)
+        ax[m] = bcast(wv, islab + m);
         ay[m] = bcast(wv, 12 + m);
         az[m] = bcast(wv, 24 + m);
         if constexpr (KI != BSPL_V) {
-            dax[m] = bcast(wv, 4 + m);
-            d2ax[m] = bcast(wv, 8 + m);
+            dax[m] = bcast(wv, 4 + islab + m);
+            d2ax[m] = bcast(wv, 8 + islab + m);
             day[m] = bcast(wv, 16 + m);
             d2ay[m] = bcast(wv, 20 + m);
             daz[m] = bcast(wv, 28 + m);
@@ -275,7 +274,7 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     // 3. gather and reduce
     const int n0 = chunk * (64 * VW) + lane * VW;
     const int valid = d.nsplines - n0;  // > 0 for lanes that own splines
-    const char* base = d.table + (size_t)i0 * d.xstride + (size_t)j0 * d.ystride +
+    const char* base = d.table + (size_t)(i0 + islab) * d.xstride + (size_t)j0 * d.ystride +
                        (size_t)k0 * d.row_bytes + (size_t)chunk * (64 * VW * EB);
     const uint32_t loff = valid > 0 ? (uint32_t)(lane * VW * EB) : 0u;
 
@@ -304,8 +303,8 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     for (int g = 0; g < DEPTH - 1; ++g) issue(g, g);
 
 #pragma unroll
-    for (int g = 0; g < 16; ++g) {
-        if (g + DEPTH - 1 < 16) issue(g + DEPTH - 1, (g + DEPTH - 1) % DEPTH);
+    for (int g = 0; g < NG; ++g) {
+        if (g + DEPTH - 1 < NG) issue(g + DEPTH - 1, (g + DEPTH - 1) % DEPTH);
         const int i = g >> 2, j = g & 3;
         if (j == 0) {
 #pragma unroll
@@ -367,7 +366,7 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
                 }
             }
         }
-        if (g + DEPTH < 16) {
+        if (g + DEPTH < NG) {
             if (j == 3) {
 #pragma unroll
                 for (int o = 0; o < NOUT; ++o)
@@ -392,7 +391,7 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
         for (int k = 0; k < 9; ++k) m[k] = d.Mf[k / 3][k % 3];
         // lane 6k + q holds the coefficient of H_u component q in H_r component k
         float hc = 0.f;
-        if (lane < 36) hc = hess_coef(m, lane / 6, lane % 6);
+        if (lane < 36) hc = hess_coef(d, lane / 6, lane % 6);
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
             out[0][e] = acc[0][e];
@@ -509,6 +508,75 @@ __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
             const int p = d.perm ? __builtin_amdgcn_readfirstlane(d.perm[q]) : q;
             eval_unit<T, VW, KIND, LAT>(d, p, chunk, lane);
         }
+    }
+}
+
+// Output row of component o (0..NO-1) of position p, in the order the
+// accumulators hold them: v; gx gy gz; then l or hxx hxy hxz hyy hyz hzz.
+template <int KIND>
+__device__ __forceinline__ float* out_row(const TableDesc& d, int o, int p) {
+    const int64_t ldo = d.ldo;
+    if (o == 0) return d.v + (int64_t)p * ldo;
+    if (o < 4) return d.g + ((int64_t)p * 3 + (o - 1)) * ldo;
+    if constexpr (KIND == BSPL_VGL) return d.lh + (int64_t)p * ldo;
+    return d.lh + ((int64_t)p * 6 + (o - 4)) * ldo;
+}
+
+// Latency mode (the GPU form of the paper's nested threading over one
+// walker's work, section "Optimizations and Parallelization"): with few
+// positions there are too few (position, tile) units to fill the chip, and
+// each unit's 16 row groups take several memory round trips in sequence.
+// Here SPLIT wavefronts share one unit: wavefront s gathers and reduces the
+// x-slabs [s*4/SPLIT, (s+1)*4/SPLIT) with all of its row groups in flight
+// at once, the partial sums meet in LDS, and wavefront s adds up and stores
+// the components o with o % SPLIT == s (partials summed in slab order, so
+// the result is deterministic).  One workgroup = wx tiles x SPLIT slabs of
+// one position; block b covers position b / xgroups.
+template <typename T, int VW, int KIND, int LAT, int SPLIT>
+__global__ void __launch_bounds__(512) split_kernel(const TableDesc d, int wx) {
+    constexpr int NO = Shape<KIND>::nout;
+    constexpr int NG = 16 / SPLIT;
+    extern __shared__ float part[];  // [SPLIT][wx][NO][VW][64]
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int wxi = wave % wx;
+    const int slab = wave / wx;
+    const int q = (int)(blockIdx.x / (unsigned)d.xgroups);
+    const int cg = (int)(blockIdx.x - (unsigned)q * (unsigned)d.xgroups);
+    const int chunk = cg * wx + wxi;
+    const bool live = chunk < d.nchunks;
+    float acc[NO][VW];
+    int n0 = 0, valid = 0;
+    const int p = d.perm ? __builtin_amdgcn_readfirstlane(d.perm[q]) : q;
+    if (live) {
+        eval_core<T, VW, KIND, LAT, NG, NG>(d, p, chunk, lane, acc, n0, valid, slab * (NG / 4));
+    } else {
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[o][e] = 0.f;
+    }
+    float* mine = part + (size_t)(slab * wx + wxi) * (NO * VW * 64);
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) mine[(o * VW + e) * 64 + lane] = acc[o][e];
+    __syncthreads();
+    if (!live || valid <= 0) return;
+    const bool vec = d.vec_store != 0;
+#pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        if (o % SPLIT != slab) continue;
+        float x[VW];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+            float sum = part[((size_t)wxi * NO * VW + o * VW + e) * 64 + lane];
+#pragma unroll
+            for (int s2 = 1; s2 < SPLIT; ++s2)
+                sum += part[((size_t)(s2 * wx + wxi) * NO * VW + o * VW + e) * 64 + lane];
+            x[e] = sum;
+        }
+        store_row<VW>(out_row<KIND>(d, o, p) + n0, x, valid, vec);
     }
 }
 
@@ -630,6 +698,50 @@ const void* pick_kernel(int vw) {
     return nullptr;
 }
 
+template <typename T, int KIND, int LAT, int SPLIT>
+const void* pick_split(int vw) {
+    if constexpr (Elem<T>::bytes == 4) {
+        switch (vw) {
+        case 1: return (const void*)&split_kernel<T, 1, KIND, LAT, SPLIT>;
+        case 2: return (const void*)&split_kernel<T, 2, KIND, LAT, SPLIT>;
+        case 4: return (const void*)&split_kernel<T, 4, KIND, LAT, SPLIT>;
+        }
+    } else {
+        switch (vw) {
+        case 2: return (const void*)&split_kernel<T, 2, KIND, LAT, SPLIT>;
+        case 4: return (const void*)&split_kernel<T, 4, KIND, LAT, SPLIT>;
+        case 8: return (const void*)&split_kernel<T, 8, KIND, LAT, SPLIT>;
+        }
+    }
+    return nullptr;
+}
+
+template <typename T, int KIND>
+const void* pick_split_kind(int vw, int lattice, int split) {
+    if (split == 2)
+        return lattice ? pick_split<T, KIND, 1, 2>(vw) : pick_split<T, KIND, 0, 2>(vw);
+    if (split == 4)
+        return lattice ? pick_split<T, KIND, 1, 4>(vw) : pick_split<T, KIND, 0, 4>(vw);
+    return nullptr;
+}
+
+const void* split_kernel_for(int dtype, int kind, int vw, int lattice, int split) {
+#define BSPL_SKINDS(T)                                                          \
+    switch (kind) {                                                             \
+    case BSPL_V: return pick_split_kind<T, BSPL_V>(vw, lattice, split);         \
+    case BSPL_VGL: return pick_split_kind<T, BSPL_VGL>(vw, lattice, split);     \
+    case BSPL_VGH: return pick_split_kind<T, BSPL_VGH>(vw, lattice, split);     \
+    }                                                                           \
+    return nullptr;
+    switch (dtype) {
+    case BSPL_F32: { BSPL_SKINDS(F32) }
+    case BSPL_F16: { BSPL_SKINDS(F16) }
+    case BSPL_BF16: { BSPL_SKINDS(BF16) }
+    }
+#undef BSPL_SKINDS
+    return nullptr;
+}
+
 template <typename T, int KIND, int MAXT>
 const void* pick_kernel_lat(int vw, int lattice) {
     return lattice ? pick_kernel<T, KIND, MAXT, 1>(vw) : pick_kernel<T, KIND, MAXT, 0>(vw);
@@ -668,8 +780,29 @@ bspl_status launch(const void* fn, const KernelArgs<MAXT>& a, const bspl_tile& t
 
 }  // namespace
 
+int64_t split_lds_bytes(int kind, int vw, int wx, int split) {
+    const int nout = kind == BSPL_V ? 1 : (kind == BSPL_VGL ? 5 : 10);
+    return (int64_t)split * wx * nout * vw * 64 * (int64_t)sizeof(float);
+}
+
 bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
                           const bspl_tile& tile, hipStream_t s) {
+    if (tile.split > 1) {
+        const void* fn = split_kernel_for(t->info.dtype, kind, tile.vw, d.lattice, tile.split);
+        if (!fn) return fail(BSPL_EINVAL, "no split kernel for this dtype/kind/vw/split");
+        const int64_t lds = split_lds_bytes(kind, tile.vw, tile.wx, tile.split);
+        if (lds > kSplitMaxLds)
+            return fail(BSPL_EINVAL, "split tile needs %lld bytes of LDS (at most %d)",
+                        (long long)lds, kSplitMaxLds);
+        const int64_t blocks = d.npos * (int64_t)d.xgroups;
+        if (blocks <= 0) return BSPL_OK;
+        TableDesc dd = d;
+        int wx = tile.wx;
+        void* args[] = {&dd, &wx};
+        BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(64 * tile.wx * tile.split), args,
+                                 (size_t)lds, s));
+        return BSPL_OK;
+    }
     KernelArgs<1> a;
     a.t[0] = d;
     a.t[0].groups_begin = 0;

@@ -110,6 +110,10 @@ struct OrderLaunch {
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o);
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s);
 
+// Latency mode: LDS bytes a split tile's partial sums take, and the limit.
+constexpr int kSplitMaxLds = 65536;
+int64_t split_lds_bytes(int kind, int vw, int wx, int split);
+
 // Interpolating coefficients: three in-place axis passes, src -> dst (src may
 // equal dst), both unpadded [nx][ny][nz][nspl] FP32 on the device.
 bspl_status launch_fit(int nx, int ny, int nz, int64_t nspl, const float* src, float* dst,
@@ -129,7 +133,11 @@ void wisdom_key(char* buf, size_t n, int dtype, int kind, int64_t nsplines,
 int device_cu_count();
 
 // Autotuner pieces shared with the batched planner (autotune.cpp).
-std::vector<bspl_tile> tile_candidates(int dtype, int64_t max_nsplines, bool persistent);
+// Candidate tiles of the sweep; split (latency-mode) tiles only for single
+// evaluations of at most kSplitMaxPositions positions.
+constexpr int64_t kSplitMaxPositions = 64;
+std::vector<bspl_tile> tile_candidates(int dtype, int kind, int64_t max_nsplines, int64_t npos,
+                                       bool persistent);
 bspl_status fill_random_positions(double* pos, int64_t npos, const double box[3], uint64_t salt,
                                   hipStream_t s);
 bspl_status sweep(const std::vector<bspl_tile>& cands, hipStream_t s,

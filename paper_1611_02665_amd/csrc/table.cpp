@@ -40,8 +40,11 @@ bool tile_valid(const bspl_tile& tile, int dtype) {
     const bool f32 = dtype == BSPL_F32;
     const bool vw_ok = f32 ? (tile.vw == 1 || tile.vw == 2 || tile.vw == 4)
                            : (tile.vw == 2 || tile.vw == 4 || tile.vw == 8);
-    return vw_ok && tile.wx >= 1 && tile.wy >= 1 && tile.wx * tile.wy <= 8 && tile.grid >= 0 &&
-           tile.order >= 0 && tile.order <= 2;
+    const bool base_ok = vw_ok && tile.wx >= 1 && tile.wy >= 1 && tile.wx * tile.wy <= 8 &&
+                         tile.grid >= 0 && tile.order >= 0 && tile.order <= 2;
+    if (tile.split == 0 || tile.split == 1) return base_ok;
+    return base_ok && (tile.split == 2 || tile.split == 4) && tile.wy == 1 && tile.grid == 0 &&
+           tile.wx * tile.split <= 8;
 }
 
 bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos) {
@@ -419,6 +422,7 @@ bspl_status spline_eval_ratio(const bspl_table* t, bspl_kind kind, int64_t npos,
         tl = *tile;
         if (!tile_valid(tl, t->info.dtype))
             return fail(BSPL_EINVAL, "tile invalid for dtype %d", t->info.dtype);
+        if (tl.split > 1) return fail(BSPL_EINVAL, "split tiles are for evaluations only");
     } else {
         tl = default_tile(t, kind, npos);
         const int64_t chunks = (t->info.n_splines + 64 * tl.vw - 1) / (64 * tl.vw);

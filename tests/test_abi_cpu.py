@@ -177,13 +177,16 @@ def test_wisdom_files(tmp_path):
         B.spline_wisdom_load(missing)
     assert e.value.status == B.BSPL_EIO
     p = tmp_path / "w.txt"
-    p.write_text("# comment\nsingle|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 1 12.5\n"
-                 "garbage line\n")
+    p.write_text("# comment\nsingle|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 1 1 12.5\n"
+                 "single|gfx950|f32|vgh|N64|16x16x16|p1 1 2 1 0 0 4\n"
+                 "garbage line\nsingle|gfx950|f32|v|N64|16x16x16|p8 1 1 1 0\n")
     B.spline_wisdom_load(str(p))
     out = str(tmp_path / "out.txt")
     B.spline_wisdom_save(out)
     text = open(out).read()
-    assert "single|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 1" in text
+    assert "single|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 1 1\n" in text
+    assert "single|gfx950|f32|vgh|N64|16x16x16|p1 1 2 1 0 0 4\n" in text
+    assert "|v|" not in text  # a line with too few fields is skipped
     with pytest.raises(B.BsplineError) as e:
         B.spline_wisdom_save(str(tmp_path / "no" / "such" / "dir.txt"))
     assert e.value.status == B.BSPL_EIO

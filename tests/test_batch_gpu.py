@@ -71,7 +71,7 @@ def test_batch_plan_replays(kind, tile):
         plan = B.spline_batch_plan_create(
             T.handles, SMALL_NPOS, kind, pd, [o["v"] for o in outs],
             [o.get("g") for o in outs], [_lh(kind, o) for o in outs], ldo, tile=tile)
-        assert B.spline_batch_plan_tile(plan).as_tuple() == tile
+        assert B.spline_batch_plan_tile(plan).as_tuple()[:5] == tile
         refs = [oracle.evaluate(kind, T.coefs[i], pos[i], box=T.boxes[i]) for i in range(4)]
         for rep in range(3):
             for o in outs:  # eager work between replays

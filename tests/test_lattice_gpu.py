@@ -53,8 +53,12 @@ def _tiles(dtype):
     i = 0
     for vw in vws:
         for wx, wy in shapes:
-            yield (vw, wx, wy, 0 if i % 2 else 5, i % 3)
+            yield (vw, wx, wy, 0 if i % 2 else 5, i % 3, 1)
             i += 1
+        for split in (2, 4):  # latency mode, within the 64 KiB of partial sums
+            if split * vw <= 16:
+                yield (vw, 1, 1, 0, i % 3, split)
+                i += 1
 
 
 @pytest.fixture(scope="module")

@@ -81,11 +81,24 @@ def test_cross_kind_consistency(cfg1):
 
 
 # ------------------------------------------------------- every tile shape
+NOUT = {"v": 1, "vgl": 5, "vgh": 10}
+
+
+def split_fits(tile, kind):
+    """A latency-mode tile's partial sums fit the 64 KiB LDS limit."""
+    vw, wx, _, _, _, split = tile
+    return split <= 1 or split * wx * NOUT[kind] * vw * 256 <= 65536
+
+
 def _tiles(dtype):
     vws = (1, 2, 4) if dtype == "f32" else (2, 4, 8)
     shapes = [(1, 1), (2, 1), (4, 1), (8, 1), (1, 2), (1, 4), (2, 2), (4, 2), (2, 4), (1, 8)]
     for i, (vw, (wx, wy), grid) in enumerate(itertools.product(vws, shapes, (0, 7))):
-        yield (vw, wx, wy, grid, i % 3)
+        yield (vw, wx, wy, grid, i % 3, 1)
+    # latency mode: split units, every order
+    for i, (vw, wx, split) in enumerate(itertools.product(vws, (1, 2, 4), (2, 4))):
+        if wx * split <= 8:
+            yield (vw, wx, 1, 0, i % 3, split)
 
 
 @pytest.fixture(scope="module")
@@ -107,6 +120,11 @@ def test_all_tiles_ragged(ragged, dtype):
     with Table(coef, dtype, box) as t:
         for tile in _tiles(dtype):
             for kind in ("v", "vgl", "vgh"):
+                if not split_fits(tile, kind):
+                    with pytest.raises(B.BsplineError) as e:
+                        run_gpu(B, t.h, kind, pos, 300, ldo=301, tile=tile)
+                    assert e.value.status == B.BSPL_EINVAL and "LDS" in str(e.value)
+                    continue
                 gpu, raw = run_gpu(B, t.h, kind, pos, 300, ldo=301, tile=tile)
                 assert_canary(raw, 300)
                 assert_close(kind, gpu, refs[kind], label=f"{dtype} tile {tile} {kind}")
@@ -115,7 +133,9 @@ def test_all_tiles_ragged(ragged, dtype):
 def test_invalid_tiles_rejected(cfg1):
     _, pos, t = cfg1
     for tile in [(3, 1, 1, 0, 0), (8, 1, 1, 0, 0), (4, 0, 1, 0, 0), (4, 4, 4, 0, 0),
-                 (4, 1, 1, -1, 0), (4, 1, 1, 0, 3), (4, 1, 1, 0, -1)]:
+                 (4, 1, 1, -1, 0), (4, 1, 1, 0, 3), (4, 1, 1, 0, -1),
+                 (1, 1, 2, 0, 0, 2), (1, 1, 1, 5, 0, 2), (1, 8, 1, 0, 0, 2), (1, 4, 1, 0, 0, 4),
+                 (1, 1, 1, 0, 0, 3), (1, 1, 1, 0, 0, -1)]:
         with pytest.raises(B.BsplineError) as e:
             run_gpu(B, t.h, "vgh", pos[:, :4], 64, tile=tile)
         assert e.value.status == B.BSPL_EINVAL
@@ -139,6 +159,82 @@ def test_order_changes_no_result(dtype):
         ref = oracle.evaluate("vgh", dequantized(coef, dtype), pos[:, :300])
         got = {k: a[:300, ..., :520].astype(np.float64) for k, a in outs[-1].items()}
         assert_close("vgh", got, ref, label=f"ordered {dtype}")
+
+
+def test_split_order_bit_identity_and_autotune():
+    """Latency mode: the evaluation order changes no bit of a split unit's
+    outputs; split and unsplit units agree to rounding; the autotuner's
+    choice for a few positions evaluates correctly."""
+    coef = synth.coef_table(20, 24, 16, 520, stream=19)
+    pos = synth.positions(4100, stream=20) * 2 - 0.5  # more than one ordering chunk
+    with Table(coef) as t:
+        outs = [run_gpu(B, t.h, "vgh", pos, 520, tile=(1, 2, 1, 0, order, 4))[1]
+                for order in (0, 1, 2)]
+        for o in outs[1:]:
+            for k in o:
+                assert np.array_equal(o[k], outs[0][k]), k
+        plain = run_gpu(B, t.h, "vgh", pos, 520, tile=(1, 2, 1, 0, 0, 1))[1]
+        for k in plain:
+            scale = np.abs(plain[k][..., :520]).max()
+            assert np.abs(plain[k][..., :520] - outs[0][k][..., :520]).max() <= 1e-6 * scale, k
+        few = pos[:, :3].copy()
+        tile = B.spline_autotune(t.h, "vgh", 3)
+        gpu, _ = run_gpu(B, t.h, "vgh", few, 520, tile=tile)
+        assert_close("vgh", gpu, oracle.evaluate("vgh", coef, few), label=f"autotuned {tile}")
+        print("autotuned tile for 3 positions:", tile)
+
+
+def test_graph_captured_evaluations_replay_exactly(cfg1):
+    """Evaluations captured into a HIP graph (plain and split units, input
+    order) replay to the same bits as eager calls, with eager work on the
+    outputs between replays."""
+    coef, pos, t = cfg1
+    dev = torch.device("cuda")
+    sets = [torch.from_numpy(np.ascontiguousarray(pos[:, 4 * i:4 * i + 4])).to(dev)
+            for i in range(4)]
+    tiles = [(1, 1, 1, 0, 0, 1), (1, 1, 1, 0, 0, 4), (1, 2, 1, 0, 0, 2), (2, 1, 1, 0, 0, 1)]
+    outs = [(torch.empty(4, 64, device=dev), torch.empty(4, 3, 64, device=dev),
+             torch.empty(4, 6, 64, device=dev)) for _ in tiles]
+
+    def run(stream):
+        for (v, g, h), p, tile in zip(outs, sets, tiles):
+            B.spline_eval(t.h, "vgh", 4, p, v, g, h, 64, tile=tile, stream=stream)
+
+    run(torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    eager = [tuple(x.clone() for x in o) for o in outs]
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(gs):
+        with torch.cuda.graph(graph, stream=gs):
+            run(gs.cuda_stream)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for o in outs:
+            for x in o:
+                x.fill_(float(rep) - 7.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            for x, y in zip(o, e):
+                assert torch.equal(x, y), rep
+
+
+def test_split_rejected_outside_single_evaluations(cfg1):
+    _, pos, t = cfg1
+    dev = torch.device("cuda")
+    p = torch.from_numpy(pos[:, :4].copy()).to(dev)
+    out = torch.empty((4, 1), dtype=torch.float64, device=dev)
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_eval_ratio(t.h, "v", 4, p, torch.zeros((4, 64), device=dev), 64, out,
+                            tile=(1, 1, 1, 0, 0, 2))
+    assert e.value.status == B.BSPL_EINVAL
+    v = torch.empty((4, 64), device=dev)
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_batch_plan_create([t.h], [4], "v", [p], [v], ldo=[64], tile=(1, 1, 1, 0, 0, 2))
+    assert e.value.status == B.BSPL_EINVAL
 
 
 # ------------------------------------------------------------ edge cases
