@@ -594,6 +594,13 @@ def cpu_baseline(np, synth, coef, budget_cpu_s=12.0, max_batches=64):
         wall += time.perf_counter() - t
         done += NPOS
         b += 1
+    # one core on one batch, for scale
+    oracle.set_num_threads(1)
+    pos = synth.positions(NPOS, stream=synth.position_stream(0), batch=0)
+    t = time.perf_counter()
+    oracle.evaluate("vgh", coef, pos)
+    one = NPOS * NSPL / (time.perf_counter() - t)
+    oracle.set_num_threads(nth)
     cpu = platform.processor() or platform.machine()
     try:
         for line in open("/proc/cpuinfo"):
@@ -606,7 +613,7 @@ def cpu_baseline(np, synth, coef, budget_cpu_s=12.0, max_batches=64):
             "kind": "oracle",
             "sample": f"eval_vgh FP64 oracle (C, OpenMP over positions), {b} batches x "
                       f"{NPOS} positions x N={NSPL} of the same 48^3 table, {wall:.2f} s wall",
-            "cpu_model": cpu, "nproc": os.cpu_count()}
+            "cpu_model": cpu, "nproc": os.cpu_count(), "single_core_value": one}
 
 
 if __name__ == "__main__":

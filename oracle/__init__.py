@@ -69,6 +69,8 @@ def _bind(path: str):
                                              ctypes.c_int64, dp, dp]
     lib.oracle_fit_interpolating.restype = ctypes.c_int
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     return lib
 
 
@@ -140,6 +142,10 @@ def locate(x: float, box_len: float, n: int):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
 
 
 def _outputs(kind, npos, ncoef):

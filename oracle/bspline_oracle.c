@@ -422,6 +422,15 @@ int oracle_num_threads(void)
 #endif
 }
 
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Interpolating coefficients (paper, "QMC and B-spline-based SPOs": the
  * coefficients are the orbitals' interpolation tables).  Reading: the
  * periodic spline must take the given value at every grid point.  At a grid

@@ -98,6 +98,9 @@ int oracle_fit_interpolating(int nx, int ny, int nz, int64_t ncoef, const double
 /* Number of OpenMP threads an oracle_eval call uses. */
 int oracle_num_threads(void);
 
+/* Set that number (n > 0) for later calls on the calling thread. */
+void oracle_set_num_threads(int n);
+
 #ifdef __cplusplus
 }
 #endif
