@@ -31,6 +31,17 @@
  *  - Outputs are FP32 device arrays; element n of component c of position p
  *    is out[(p*ncomp + c)*ldo + n] with ldo >= N.  Columns [0,N) are
  *    overwritten (never accumulated into); columns [N,ldo) are not touched.
+ *  - A table belongs to the device that was current when it was created;
+ *    calls that use it must run with that device current.
+ *
+ * Errors common to every evaluation entry point (spline_eval*, the batch
+ * plan calls): EINVAL for a NULL table, an unknown kind, npos < 0, ldo < N,
+ * a NULL position or output buffer while npos > 0, an invalid tile, or a
+ * table of another device; EUNSUPPORTED for npos >= 2^31 or more than 2^31
+ * work blocks; EDEVICE when a HIP call fails (the launch itself; faults
+ * inside a kernel surface at the next synchronising HIP call, as for any
+ * asynchronous work).  npos = 0 is a successful no-op.  After an argument
+ * error (EINVAL, EUNSUPPORTED) nothing has been launched.
  */
 #ifndef BSPLINE_H
 #define BSPLINE_H

@@ -307,7 +307,7 @@ bspl_status spline_batch_plan_create(bspl_plan** out, int ntables, const bspl_ta
         batch_key(*p, key, sizeof key);
         bspl_tile t;
         if (wisdom_path) (void)spline_wisdom_load(wisdom_path);
-        if (wisdom_lookup(key, &t) && tile_valid(t, p->dtype)) {
+        if (wisdom_lookup(key, &t) && tile_valid(t, p->dtype) && t.split <= 1) {
             p->tile = t;
         } else {
             float us = 0;

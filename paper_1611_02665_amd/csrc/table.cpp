@@ -70,6 +70,12 @@ static bool aligned(const void* p, int bytes) {
 
 bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, float* v, float* g,
                       float* lh, int64_t ldo, int vw, int wx, int wy, TableDesc* out) {
+    // a table's memory belongs to the device it was created on
+    int dev = -1;
+    BSPL_HIP(hipGetDevice(&dev));
+    if (dev != t->device)
+        return fail(BSPL_EINVAL, "the table lives on device %d but device %d is current",
+                    t->device, dev);
     const bspl_table_info& in = t->info;
     TableDesc d{};
     d.table = static_cast<const char*>(t->d_table);
@@ -381,8 +387,9 @@ bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const
     if (tile) {
         tl = *tile;
         if (!tile_valid(tl, t->info.dtype))
-            return fail(BSPL_EINVAL, "tile (vw=%d wx=%d wy=%d grid=%d) invalid for dtype %d",
-                        tl.vw, tl.wx, tl.wy, tl.grid, t->info.dtype);
+            return fail(BSPL_EINVAL,
+                        "tile (vw=%d wx=%d wy=%d grid=%d order=%d split=%d) invalid for dtype %d",
+                        tl.vw, tl.wx, tl.wy, tl.grid, tl.order, tl.split, t->info.dtype);
     } else {
         spline_tile_select(t, kind, npos, &tl);
     }
