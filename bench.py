@@ -37,7 +37,9 @@ NSPL = 2048
 NPOS = 512
 NBATCH = 16
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_eval_vgh_f32_48cubed_N2048_512pos.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1611_02665_amd", "csrc", "eval_kernels.hip")
+# sources of the FP32 evaluation kernel (the one the counter profile covers)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1611_02665_amd", "csrc", f)
+               for f in ("eval_device.hpp", "eval_f32.hip", "internal.hpp")]
 # Tile wisdom for gfx950, written by the autotuner (python bench.py --retune)
 WISDOM_FILE = os.path.join(ROOT, "paper_1611_02665_amd", "wisdom_gfx950.txt")
 
@@ -47,8 +49,11 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(per_launch_alg_bytes, tile):

@@ -14,8 +14,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbspline.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["table.cpp", "eval_kernels.hip", "layout_kernels.hip", "order_kernels.hip",
-           "fit_kernels.hip", "autotune.cpp", "batch.cpp"]
+SOURCES = ["eval_f32.hip", "eval_f16.hip", "eval_bf16.hip", "eval_launch.hip", "table.cpp",
+           "layout_kernels.hip", "order_kernels.hip", "fit_kernels.hip", "autotune.cpp",
+           "batch.cpp"]
 ARCH = os.environ.get("BSPL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -39,7 +40,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(os.cpu_count() or 4, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -13,8 +13,14 @@
 //     are one coalesced load per row (16 bytes per lane at VW=4/FP32), and
 //     the reduction runs z first, then y, then x, all in FP32 registers.
 //  4. The 1, 5 or 10 output rows are written once, SoA.
-// The path is HBM-bound (about 2 flop/byte), so there is no MFMA and no LDS:
-// every byte moves once from HBM to registers.
+// The path is HBM-bound (about 2 flop/byte), so there is no MFMA, and LDS
+// only carries the partial sums of split (latency-mode) units: every table
+// byte moves once from HBM to registers.
+//
+// This header holds the device code and the generic kernel pickers; the
+// three dtype translation units instantiate it.
+#pragma once
+
 #include <type_traits>
 
 #include "internal.hpp"
@@ -663,23 +669,6 @@ const void* pick_ratio_lat(int vw, int lattice) {
     return lattice ? pick_ratio<T, KIND, 1>(vw) : pick_ratio<T, KIND, 0>(vw);
 }
 
-const void* ratio_kernel_for(int dtype, int kind, int vw, int lattice) {
-#define BSPL_RKINDS(T)                                                    \
-    switch (kind) {                                                       \
-    case BSPL_V: return pick_ratio_lat<T, BSPL_V>(vw, lattice);           \
-    case BSPL_VGL: return pick_ratio_lat<T, BSPL_VGL>(vw, lattice);       \
-    case BSPL_VGH: return pick_ratio_lat<T, BSPL_VGH>(vw, lattice);       \
-    }                                                                     \
-    return nullptr;
-    switch (dtype) {
-    case BSPL_F32: { BSPL_RKINDS(F32) }
-    case BSPL_F16: { BSPL_RKINDS(F16) }
-    case BSPL_BF16: { BSPL_RKINDS(BF16) }
-    }
-#undef BSPL_RKINDS
-    return nullptr;
-}
-
 template <typename T, int KIND, int MAXT, int LAT>
 const void* pick_kernel(int vw) {
     if constexpr (Elem<T>::bytes == 4) {
@@ -725,125 +714,45 @@ const void* pick_split_kind(int vw, int lattice, int split) {
     return nullptr;
 }
 
-const void* split_kernel_for(int dtype, int kind, int vw, int lattice, int split) {
-#define BSPL_SKINDS(T)                                                          \
-    switch (kind) {                                                             \
-    case BSPL_V: return pick_split_kind<T, BSPL_V>(vw, lattice, split);         \
-    case BSPL_VGL: return pick_split_kind<T, BSPL_VGL>(vw, lattice, split);     \
-    case BSPL_VGH: return pick_split_kind<T, BSPL_VGH>(vw, lattice, split);     \
-    }                                                                           \
-    return nullptr;
-    switch (dtype) {
-    case BSPL_F32: { BSPL_SKINDS(F32) }
-    case BSPL_F16: { BSPL_SKINDS(F16) }
-    case BSPL_BF16: { BSPL_SKINDS(BF16) }
-    }
-#undef BSPL_SKINDS
-    return nullptr;
-}
-
 template <typename T, int KIND, int MAXT>
 const void* pick_kernel_lat(int vw, int lattice) {
     return lattice ? pick_kernel<T, KIND, MAXT, 1>(vw) : pick_kernel<T, KIND, MAXT, 0>(vw);
 }
 
-template <int MAXT>
-const void* kernel_for(int dtype, int kind, int vw, int lattice) {
-#define BSPL_KINDS(T)                                                      \
-    switch (kind) {                                                        \
-    case BSPL_V: return pick_kernel_lat<T, BSPL_V, MAXT>(vw, lattice);     \
-    case BSPL_VGL: return pick_kernel_lat<T, BSPL_VGL, MAXT>(vw, lattice); \
-    case BSPL_VGH: return pick_kernel_lat<T, BSPL_VGH, MAXT>(vw, lattice); \
-    }                                                                      \
-    return nullptr;
-    switch (dtype) {
-    case BSPL_F32: { BSPL_KINDS(F32) }
-    case BSPL_F16: { BSPL_KINDS(F16) }
-    case BSPL_BF16: { BSPL_KINDS(BF16) }
-    }
-#undef BSPL_KINDS
-    return nullptr;
-}
-
-template <int MAXT>
-bspl_status launch(const void* fn, const KernelArgs<MAXT>& a, const bspl_tile& tile,
-                   hipStream_t s) {
-    if (!fn) return fail(BSPL_EINVAL, "no kernel for this dtype/kind/vw");
-    if (a.total_groups <= 0) return BSPL_OK;
-    int64_t grid = a.total_groups;
-    if (tile.grid > 0 && tile.grid < grid) grid = tile.grid;
-    dim3 block(64 * tile.wx * tile.wy);
-    void* args[] = {const_cast<KernelArgs<MAXT>*>(&a)};
-    BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), block, args, 0, s));
-    return BSPL_OK;
-}
-
 }  // namespace
-
-int64_t split_lds_bytes(int kind, int vw, int wx, int split) {
-    const int nout = kind == BSPL_V ? 1 : (kind == BSPL_VGL ? 5 : 10);
-    return (int64_t)split * wx * nout * vw * 64 * (int64_t)sizeof(float);
-}
-
-bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
-                          const bspl_tile& tile, hipStream_t s) {
-    if (tile.split > 1) {
-        const void* fn = split_kernel_for(t->info.dtype, kind, tile.vw, d.lattice, tile.split);
-        if (!fn) return fail(BSPL_EINVAL, "no split kernel for this dtype/kind/vw/split");
-        const int64_t lds = split_lds_bytes(kind, tile.vw, tile.wx, tile.split);
-        if (lds > kSplitMaxLds)
-            return fail(BSPL_EINVAL, "split tile needs %lld bytes of LDS (at most %d)",
-                        (long long)lds, kSplitMaxLds);
-        const int64_t blocks = d.npos * (int64_t)d.xgroups;
-        if (blocks <= 0) return BSPL_OK;
-        TableDesc dd = d;
-        int wx = tile.wx;
-        void* args[] = {&dd, &wx};
-        BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)blocks), dim3(64 * tile.wx * tile.split), args,
-                                 (size_t)lds, s));
-        return BSPL_OK;
-    }
-    KernelArgs<1> a;
-    a.t[0] = d;
-    a.t[0].groups_begin = 0;
-    a.ntables = 1;
-    a.wx = tile.wx;
-    a.wy = tile.wy;
-    a.xcd_remap = tile.order == 2 ? 1 : 0;
-    const int64_t ygroups = (d.npos + tile.wy - 1) / tile.wy;
-    a.total_groups = ygroups * d.xgroups;
-    return launch<1>(kernel_for<1>(t->info.dtype, kind, tile.vw, d.lattice), a, tile, s);
-}
-
-static int any_lattice(const KernelArgs<kMaxTables>& a) {
-    for (int i = 0; i < a.ntables; ++i)
-        if (a.t[i].lattice) return 1;
-    return 0;
-}
-
-bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
-                         const bspl_tile& tile, hipStream_t s) {
-    return launch<kMaxTables>(kernel_for<kMaxTables>(dtype, kind, tile.vw, any_lattice(a)), a,
-                              tile, s);
-}
-
-const void* multi_kernel_ptr(int dtype, int kind, int vw, int lattice) {
-    return kernel_for<kMaxTables>(dtype, kind, vw, lattice);
-}
-
-bspl_status launch_ratio(const bspl_table* t, int kind, const TableDesc& d, const float* ainv,
-                         int64_t ld_ainv, double* out, const bspl_tile& tile, hipStream_t s) {
-    const void* fn = ratio_kernel_for(t->info.dtype, kind, tile.vw, d.lattice);
-    if (!fn) return fail(BSPL_EINVAL, "no ratio kernel for this dtype/kind/vw");
-    if (d.npos <= 0) return BSPL_OK;
-    int waves = tile.wx < d.nchunks ? tile.wx : d.nchunks;
-    if (waves < 1) waves = 1;
-    int64_t grid = d.npos;
-    if (tile.grid > 0 && tile.grid < grid) grid = tile.grid;
-    TableDesc dd = d;
-    void* args[] = {&dd, const_cast<float**>(&ainv), &ld_ainv, &out};
-    BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64 * waves), args, 0, s));
-    return BSPL_OK;
-}
-
 }  // namespace bspl
+
+// The kernels of one table dtype, by kind, vector width, lattice form and
+// split: each dtype's translation unit instantiates them (eval_f32.hip,
+// eval_f16.hip, eval_bf16.hip) so that the three compile in parallel.
+#define BSPL_DEFINE_KERNEL_TABLE(T)                                                        \
+    const void* eval_kernel_ptr_##T(int kind, int vw, int multi, int lattice) {            \
+        switch (kind) {                                                                    \
+        case BSPL_V:                                                                       \
+            return multi ? pick_kernel_lat<T, BSPL_V, kMaxTables>(vw, lattice)             \
+                         : pick_kernel_lat<T, BSPL_V, 1>(vw, lattice);                     \
+        case BSPL_VGL:                                                                     \
+            return multi ? pick_kernel_lat<T, BSPL_VGL, kMaxTables>(vw, lattice)           \
+                         : pick_kernel_lat<T, BSPL_VGL, 1>(vw, lattice);                   \
+        case BSPL_VGH:                                                                     \
+            return multi ? pick_kernel_lat<T, BSPL_VGH, kMaxTables>(vw, lattice)           \
+                         : pick_kernel_lat<T, BSPL_VGH, 1>(vw, lattice);                   \
+        }                                                                                  \
+        return nullptr;                                                                    \
+    }                                                                                      \
+    const void* split_kernel_ptr_##T(int kind, int vw, int lattice, int split) {           \
+        switch (kind) {                                                                    \
+        case BSPL_V: return pick_split_kind<T, BSPL_V>(vw, lattice, split);                \
+        case BSPL_VGL: return pick_split_kind<T, BSPL_VGL>(vw, lattice, split);            \
+        case BSPL_VGH: return pick_split_kind<T, BSPL_VGH>(vw, lattice, split);            \
+        }                                                                                  \
+        return nullptr;                                                                    \
+    }                                                                                      \
+    const void* ratio_kernel_ptr_##T(int kind, int vw, int lattice) {                      \
+        switch (kind) {                                                                    \
+        case BSPL_V: return pick_ratio_lat<T, BSPL_V>(vw, lattice);                        \
+        case BSPL_VGL: return pick_ratio_lat<T, BSPL_VGL>(vw, lattice);                    \
+        case BSPL_VGH: return pick_ratio_lat<T, BSPL_VGH>(vw, lattice);                    \
+        }                                                                                  \
+        return nullptr;                                                                    \
+    }

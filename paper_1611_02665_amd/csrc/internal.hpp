@@ -82,7 +82,7 @@ bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, floa
 bool tile_valid(const bspl_tile& tile, int dtype);
 bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos);
 
-// Kernel launchers (eval_kernels.hip).
+// Kernel launchers (eval_launch.hip; kernels in eval_device.hpp).
 bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
                           const bspl_tile& tile, hipStream_t s);
 bspl_status launch_multi(int dtype, int kind, const KernelArgs<kMaxTables>& a,
