@@ -137,3 +137,19 @@ def padded_layout(coef, np_):
     out = np.zeros((nx + 3, ny + 3, nz + 3, np_), dtype=coef.dtype)
     out[..., :n] = p
     return out
+
+
+def smooth_grid_values(dims, n, seed):
+    """Band-limited periodic orbitals sampled on the grid: each of the n
+    columns is a sum of three random Fourier modes with |k_d| <= 2 (the
+    smooth data interpolation tables are built from)."""
+    rng = np.random.default_rng(seed)
+    idx = np.meshgrid(*[np.arange(d) / d for d in dims], indexing="ij")
+    out = np.zeros(tuple(dims) + (n,))
+    for s in range(n):
+        for _ in range(3):
+            k = rng.integers(-2, 3, 3)
+            ph = rng.uniform(0, 2 * np.pi)
+            out[..., s] += rng.uniform(-1, 1) * np.cos(
+                2 * np.pi * (k[0] * idx[0] + k[1] * idx[1] + k[2] * idx[2]) + ph)
+    return out.astype(np.float32)

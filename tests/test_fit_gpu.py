@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import assert_close, run_gpu
+from helpers import assert_close, run_gpu, smooth_grid_values
 
 pytestmark = pytest.mark.gpu
 
@@ -42,20 +42,6 @@ def _rel_err(got, ref):
     return float(np.abs(got.astype(np.float64) - ref).max() / np.abs(ref).max())
 
 
-def _smooth_values(dims, n, seed):
-    """Band-limited periodic orbitals: a few random Fourier modes each."""
-    rng = np.random.default_rng(seed)
-    idx = np.meshgrid(*[np.arange(d) / d for d in dims], indexing="ij")
-    out = np.zeros(tuple(dims) + (n,))
-    for s in range(n):
-        for _ in range(3):
-            k = rng.integers(-2, 3, 3)
-            ph = rng.uniform(0, 2 * np.pi)
-            out[..., s] += rng.uniform(-1, 1) * np.cos(
-                2 * np.pi * (k[0] * idx[0] + k[1] * idx[1] + k[2] * idx[2]) + ph)
-    return out.astype(np.float32)
-
-
 @pytest.mark.parametrize("shape", [(7, 9, 5, 300), (1, 2, 3, 5), (2, 1, 40, 64),
                                    (100, 3, 2, 70), (33, 31, 32, 17), (48, 48, 60, 128),
                                    (300, 2, 1, 5), (2, 3, 260, 70)])
@@ -70,7 +56,7 @@ def test_fit_matches_oracle(shape):
 
 
 def test_fit_smooth_values():
-    values = _smooth_values((12, 10, 14), 9, seed=102)
+    values = smooth_grid_values((12, 10, 14), 9, seed=102)
     ref = oracle.fit_interpolating(values.astype(np.float64))
     assert _rel_err(_gpu_fit(values), ref) <= FIT_TOL
 
