@@ -343,12 +343,12 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
                    k, warmup)
         # input (random) order only: the paper's access pattern, no row reuse
         in_tile, ms_in = best_input_order(torch, B, t, dt, npos, pp, nb, v, g, h, stream, warmup)
-        # the batched form: the same work as one persistent launch replayed
+        # the batched form: the same work as one launch replayed
         # from a HIP graph (the plan's tile comes from its own autotuning),
-        # and the same with the best input-order tile on a persistent grid
+        # and the same with the best input-order tile
         ms_b, ptile = plan_time(torch, B, t, npos, batches, v, g, h, None, stream, k, warmup)
         ms_bi, _ = plan_time(torch, B, t, npos, batches, v, g, h,
-                             tuple(in_tile[:3]) + (2048, 0), stream, k, warmup)
+                             tuple(in_tile[:3]) + (0, 0, 1), stream, k, warmup)
         # error on 64 positions against the FP32-table outputs
         B.spline_eval_vgh(t, 64, sample_d.data_ptr(), v.data_ptr(), g.data_ptr(), h.data_ptr(),
                           NSPL, stream)
@@ -425,7 +425,7 @@ CFG4 = [((32, 32, 32), 256, 97), ((40, 40, 40), 512, 512), ((48, 48, 48), 1152, 
 
 
 def batched_extra(torch, B, A, synth, steps, warmup):
-    """Four tables of uneven shape and batch size in one persistent launch
+    """Four tables of uneven shape and batch size in one launch
     replayed from a HIP graph, FP32 and FP16 tables."""
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
@@ -440,7 +440,7 @@ def batched_extra(torch, B, A, synth, steps, warmup):
     evals = sum(n * m for (_, n, m) in CFG4)
     res = {"evals_per_replay": evals,
            "workload": "eval_vgh, tables 32^3xN=256, 40^3xN=512, 48^3xN=1152, 64^3xN=2048 "
-                       "with 97/512/1500/3000 uniform positions, one persistent launch per "
+                       "with 97/512/1500/3000 uniform positions, one launch per "
                        "replay, 2 position sets alternated"}
     for dt in ("f32", "f16"):
         tabs = [B.spline_table_create(*grid, n, c, dt) for (grid, n, _), c in zip(CFG4, coefs)]

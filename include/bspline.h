@@ -265,8 +265,9 @@ bspl_status spline_wisdom_load(const char* path);
 /* Write the whole wisdom cache to a file (EIO on failure). */
 bspl_status spline_wisdom_save(const char* path);
 
-/* Batched evaluation of several tables in one persistent launch, replayed
- * from a captured HIP graph (paper: independent AoSoA tiles and walkers,
+/* Batched evaluation of several tables in one kernel launch (a grid that
+ * covers every unit, or grid > 0 persistent workgroups striding over
+ * them), replayed from a captured HIP graph (paper: independent AoSoA tiles and walkers,
  * section "Optimizations and Parallelization", Fig. 6).  All tables must
  * share one dtype.  npos[i] positions go to table i.  Buffers are bound at
  * plan creation:
@@ -274,8 +275,9 @@ bspl_status spline_wisdom_save(const char* path);
  *   v[i]     device [npos[i]][ldo[i]]
  *   g[i]     device [npos[i]][3][ldo[i]]           (VGL, VGH; else NULL)
  *   lh[i]    device l or h as for spline_eval       (VGL, VGH; else NULL)
- * tile: one decomposition for the whole launch, or NULL to autotune it at
- * plan creation (consulting and extending wisdom_path when not NULL).
+ * tile: one decomposition for the whole launch (split must be 0 or 1), or
+ * NULL to autotune it at plan creation (consulting and extending
+ * wisdom_path when not NULL).
  * Tables and buffers must outlive the plan.  At most 16 tables.           */
 bspl_status spline_batch_plan_create(bspl_plan** out, int ntables,
                                      const bspl_table* const* tables,

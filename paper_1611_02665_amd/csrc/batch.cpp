@@ -1,4 +1,4 @@
-// Batched multi-table evaluation: one persistent launch over a flattened
+// Batched multi-table evaluation: one launch over a flattened
 // work list of (table, position block, spline-tile block) units, built once
 // into a HIP graph and replayed.
 //
@@ -175,8 +175,9 @@ bspl_status autotune_plan(bspl_plan* p, hipStream_t s, bspl_tile* best, float* u
     }
     if (st == BSPL_OK) {
         std::vector<bspl_tile> cands;
+        // one grid over all units, or persistent workgroups striding over them
         for (const bspl_tile& t : tile_candidates(p->dtype, p->kind, max_n, 0, true))
-            if (t.grid > 0) cands.push_back(t);  // persistent launches only
+            cands.push_back(t);
         st = sweep(cands, s, run_batch, &c, best, us);
     }
     (void)hipStreamSynchronize(s);
