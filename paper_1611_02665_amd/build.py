@@ -53,6 +53,28 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+
+
+DEMO_SRC = os.path.join(ROOT, "tests", "c_abi_demo.c")
+DEMO_BIN = os.path.join(ROOT, "tests", "c_abi_demo")
+
+
+def build_c_demo(verbose: bool = False) -> str:
+    """The plain-C use of the ABI that the tests run (host C, gcc)."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-I", INCLUDE, "-I", os.path.join(rocm, "include"),
+           "-D__HIP_PLATFORM_AMD__", DEMO_SRC, "-o", DEMO_BIN, "-L", PKG, "-lbspline",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN/../paper_1611_02665_amd",
+           "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"gcc failed for the C demo:\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {DEMO_BIN}")
+    return DEMO_BIN
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_c_demo(verbose=True)
     sys.exit(0)
