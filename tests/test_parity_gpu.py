@@ -8,6 +8,7 @@ coefficients to a stated bound (2e-3 FP16, 5e-3 BF16).
 """
 
 import itertools
+import os
 
 import numpy as np
 import pytest
@@ -436,15 +437,44 @@ def test_reduced_precision_paper_scale(paper_table, dtype, bound):
     assert max(errs.values()) <= bound, errs
 
 
+def _bench_tile(t, kind, npos):
+    """The decomposition the benchmark times: the committed gfx950 wisdom
+    when it holds this shape, else the built-in default."""
+    import bench
+    if os.path.exists(bench.WISDOM_FILE):
+        B.spline_wisdom_load(bench.WISDOM_FILE)
+    return B.spline_tile_select(t, kind, npos)
+
+
 @pytest.mark.parametrize("kind", ["vgh", "vgl"])
 def test_config2_paper_scale_fp32(paper_table, kind):
+    """All 512 x 2048 outputs of the benchmark's first batch, in the
+    benchmark's launch configuration and in the default one."""
     coef = paper_table
     pos = synth.positions(512, stream=synth.position_stream(0))
-    with Table(coef) as t:
-        gpu, _ = run_gpu(B, t.h, kind, pos, 2048)
     ref = oracle.evaluate(kind, coef, pos)
-    errs = assert_close(kind, gpu, ref, label=f"config2 {kind}")
-    print(kind, {k: f"{e:.2e}" for k, e in errs.items()})
+    with Table(coef) as t:
+        for tile in (_bench_tile(t.h, kind, 512), None):
+            gpu, _ = run_gpu(B, t.h, kind, pos, 2048, tile=tile)
+            errs = assert_close(kind, gpu, ref, label=f"config2 {kind} {tile}")
+            print(kind, tile, {k: f"{e:.2e}" for k, e in errs.items()})
+
+
+@pytest.mark.parametrize("dtype,bound", [("f16", 2e-3), ("bf16", 5e-3)])
+def test_config3_full_batch_autotuned(paper_table, dtype, bound):
+    """4096 positions in one launch at the autotuned tile (as the benchmark
+    runs them); 256 sampled positions against the oracle."""
+    coef = paper_table
+    pos = synth.positions(4096, stream=synth.position_stream(0), batch=100)
+    idx = np.sort(np.random.default_rng(19).choice(4096, 256, replace=False))
+    with Table(coef, dtype) as t:
+        tile = B.spline_autotune(t.h, "vgh", 4096)
+        gpu, _ = run_gpu(B, t.h, "vgh", pos, 2048, tile=tile, canary=False)
+    got = {k: a[idx] for k, a in gpu.items()}
+    assert_close("vgh", got, oracle.evaluate("vgh", dequantized(coef, dtype), pos[:, idx]),
+                 label=f"config3 {dtype} {tile}")
+    errs = normalized_errors("vgh", got, oracle.evaluate("vgh", coef, pos[:, idx]))
+    assert max(errs.values()) <= bound, errs
 
 
 # ------------------------------------------------------------ streams
