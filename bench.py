@@ -130,12 +130,16 @@ def main(argv=None):
     ap.add_argument("--sweep", action="store_true",
                     help="throughput vs N (128..4096 at 48^3) and vs tile size at N=2048, "
                          "one JSON line each, instead of the benchmark line")
+    ap.add_argument("--dtype", default="f32", choices=("f32", "f16", "bf16"),
+                    help="profiling: table dtype of the --profile run")
+    ap.add_argument("--batched", action="store_true",
+                    help="profiling: the four-table plan (autotuned, or --tile), 20 replays")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args(argv)
 
-    if args.npos != NPOS and not args.profile:
-        ap.error("--npos is for --profile runs only")
+    if (args.npos != NPOS or args.dtype != "f32" or args.batched) and not args.profile:
+        ap.error("--npos, --dtype and --batched are for --profile runs only")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the evaluation "
               "shards by replicating the table and splitting positions, with no "
@@ -156,11 +160,13 @@ def main(argv=None):
         gbs, ms = copy_probe(torch)
         print(json.dumps({"copy_probe_bytes": 1 << 30, "copy_ms": ms, "copy_gbs": gbs}))
         return 0
+    if args.batched:
+        return batched_profile(torch, B, A, synth, args)
 
     t0 = time.time()
     coef = synth.coef_table(*GRID, NSPL, stream=synth.table_stream(0))
     log(f"[bench] coefficients generated in {time.time() - t0:.1f}s")
-    t32 = B.spline_table_create(*GRID, NSPL, coef, "f32")
+    t32 = B.spline_table_create(*GRID, NSPL, coef, args.dtype)
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
     npos = args.npos
@@ -181,7 +187,8 @@ def main(argv=None):
     else:
         # the tile the autotuner chose for this shape on this architecture,
         # else a live sweep (recorded in the in-process wisdom)
-        tile_source = "wisdom" if wisdom_holds(torch, "vgh", npos) else "autotune"
+        tile_source = ("wisdom" if args.dtype == "f32" and wisdom_holds(torch, "vgh", npos)
+                       else "autotune")
         if tile_source == "wisdom":
             B.spline_wisdom_load(WISDOM_FILE)
             tile = B.spline_tile_select(t32, "vgh", npos)
@@ -199,7 +206,7 @@ def main(argv=None):
     ms = timed(torch, vgh_step, steps, warmup)
     evals = npos * NSPL
     value = evals / (ms * 1e-3)
-    alg_bytes = A.batch_bytes("vgh", "f32", npos, NSPL)
+    alg_bytes = A.batch_bytes("vgh", args.dtype, npos, NSPL)
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     log(f"[bench] VGH {ms * 1e3:.2f} us/launch, {value:.4g} evals/s, {achieved:.0f} GB/s")
     if args.profile:
@@ -422,6 +429,32 @@ def plan_time(torch, B, t, npos, batches, v, g, h, tile, stream, k, warmup):
 
 CFG4 = [((32, 32, 32), 256, 97), ((40, 40, 40), 512, 512), ((48, 48, 48), 1152, 1500),
         ((64, 64, 64), 2048, 3000)]
+
+
+def batched_profile(torch, B, A, synth, args):
+    """The four-table plan alone (for counter and trace runs): autotuned or
+    --tile, 5 warm-up and 20 timed replays of one position set."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    tabs = [B.spline_table_create(*grid, n, synth.coef_table(*grid, n, stream=synth.table_stream(i)),
+                                  args.dtype) for i, (grid, n, _) in enumerate(CFG4)]
+    npos = [c[2] for c in CFG4]
+    pos = [torch.from_numpy(synth.positions(m, stream=synth.position_stream(i))).to(dev)
+           for i, m in enumerate(npos)]
+    outs = [(torch.empty(m, n, device=dev), torch.empty(m, 3, n, device=dev),
+             torch.empty(m, 6, n, device=dev)) for (_, n, m) in CFG4]
+    tile = B.bspl_tile(*[int(x) for x in args.tile.split(",")]) if args.tile else None
+    plan = B.spline_batch_plan_create(tabs, npos, "vgh", pos, [o[0] for o in outs],
+                                      [o[1] for o in outs], [o[2] for o in outs],
+                                      [n for (_, n, _) in CFG4], tile=tile, stream=stream)
+    ms = timed(torch, lambda i: B.spline_batch_execute(plan, stream), 20, 5)
+    alg = sum(A.batch_bytes("vgh", args.dtype, m, n) for (_, n, m) in CFG4)
+    log(f"[bench] batched {args.dtype} plan tile {B.spline_batch_plan_tile(plan)}: "
+        f"{ms * 1e3:.1f} us/replay, {alg / (ms * 1e-3) / 1e9:.0f} GB/s")
+    B.spline_batch_plan_destroy(plan)
+    for t in tabs:
+        B.spline_table_destroy(t)
+    return 0
 
 
 def batched_extra(torch, B, A, synth, steps, warmup):

@@ -29,8 +29,9 @@ struct bspl_plan {
     bspl::KernelArgs<bspl::kMaxTables> args{};
     int32_t* d_perm = nullptr;               // cell orders of all tables (order > 0)
     int64_t perm_off[bspl::kMaxTables] = {};
-    bspl::OrderLaunch order[bspl::kMaxTables];
-    hipGraphNode_t order_node[bspl::kMaxTables] = {};
+    bspl::OrderTables otab{};                // the ordering launch's argument (order > 0)
+    void* oargs[1] = {};
+    hipGraphNode_t order_node = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t node = nullptr;
@@ -40,6 +41,7 @@ struct bspl_plan {
 namespace bspl {
 
 static_assert(sizeof(KernelArgs<kMaxTables>) <= 4096, "kernel arguments must fit 4 KiB");
+static_assert(sizeof(OrderTables) <= 4096, "kernel arguments must fit 4 KiB");
 
 namespace {
 
@@ -127,10 +129,12 @@ bspl_status run_batch(void* vctx, const bspl_tile& tile, int it) {
     KernelArgs<kMaxTables> a;
     bspl_status st = build_args(*c->p, tile, c->b[it & 1], &a, c->perm);
     if (st != BSPL_OK) return st;
-    if (tile.order > 0)
-        for (int i = 0; i < c->p->ntables && st == BSPL_OK; ++i)
-            st = launch_order(a.t[i], const_cast<int32_t*>(a.t[i].perm), c->s);
-    if (st != BSPL_OK) return st;
+    if (tile.order > 0) {
+        OrderTables o;
+        order_tables_config(a, &o);
+        st = launch_order_tables(o, c->s);
+        if (st != BSPL_OK) return st;
+    }
     return launch_multi(c->p->dtype, c->p->kind, a, tile, c->s);
 }
 
@@ -185,30 +189,32 @@ bspl_status autotune_plan(bspl_plan* p, hipStream_t s, bspl_tile* best, float* u
     return st;
 }
 
-hipKernelNodeParams order_params(bspl_plan* p, int i) {
-    order_launch_config(p->args.t[i], const_cast<int32_t*>(p->args.t[i].perm), &p->order[i]);
-    hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(order_kernel_ptr());
-    kp.gridDim = dim3(p->order[i].grid);
-    kp.blockDim = dim3(p->order[i].block);
-    kp.sharedMemBytes = p->order[i].shmem;
-    kp.kernelParams = p->order[i].args;
-    kp.extra = nullptr;
-    return kp;
+// The ordering node's launch: every table's chunks in one grid.  Returns
+// false when no table has positions to order.
+bool order_params(bspl_plan* p, hipKernelNodeParams* kp) {
+    const int64_t chunks = order_tables_config(p->args, &p->otab);
+    p->oargs[0] = &p->otab;
+    *kp = hipKernelNodeParams{};
+    kp->func = const_cast<void*>(order_tables_kernel_ptr());
+    kp->gridDim = dim3((unsigned)std::max<int64_t>(chunks, 1));
+    kp->blockDim = dim3(order_block_threads());
+    kp->sharedMemBytes = 0;
+    kp->kernelParams = p->oargs;
+    kp->extra = nullptr;
+    return chunks > 0;
 }
 
-// Graph: [one ordering node per table (order > 0)] -> one evaluation node.
+// Graph: [one ordering node for all tables (order > 0)] -> one evaluation node.
 bspl_status instantiate(bspl_plan* p) {
     const void* fn = multi_kernel_ptr(p->dtype, p->kind, p->tile.vw, plan_lattice(*p));
     if (!fn) return fail(BSPL_EINVAL, "no batched kernel for vw=%d", p->tile.vw);
     BSPL_HIP(hipGraphCreate(&p->graph, 0));
     std::vector<hipGraphNode_t> deps;
     if (p->tile.order > 0) {
-        for (int i = 0; i < p->ntables; ++i) {
-            if (p->npos[i] == 0) continue;
-            hipKernelNodeParams op = order_params(p, i);
-            BSPL_HIP(hipGraphAddKernelNode(&p->order_node[i], p->graph, nullptr, 0, &op));
-            deps.push_back(p->order_node[i]);
+        hipKernelNodeParams op;
+        if (order_params(p, &op)) {
+            BSPL_HIP(hipGraphAddKernelNode(&p->order_node, p->graph, nullptr, 0, &op));
+            deps.push_back(p->order_node);
         }
     }
     hipKernelNodeParams kp{};
@@ -335,12 +341,10 @@ bspl_status spline_batch_execute(bspl_plan* p, void* stream) {
     if (!p) return fail(BSPL_EINVAL, "plan is NULL");
     if (p->args.total_groups == 0) return BSPL_OK;
     if (p->dirty) {
-        if (p->tile.order > 0) {
-            for (int i = 0; i < p->ntables; ++i) {
-                if (!p->order_node[i]) continue;
-                hipKernelNodeParams op = order_params(p, i);
-                BSPL_HIP(hipGraphExecKernelNodeSetParams(p->exec, p->order_node[i], &op));
-            }
+        if (p->order_node) {
+            hipKernelNodeParams op;
+            order_params(p, &op);
+            BSPL_HIP(hipGraphExecKernelNodeSetParams(p->exec, p->order_node, &op));
         }
         hipKernelNodeParams kp{};
         void* params[] = {&p->args};

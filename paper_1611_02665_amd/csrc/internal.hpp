@@ -110,6 +110,26 @@ struct OrderLaunch {
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o);
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s);
 
+// The cell orders of several tables' positions in one launch (batch plans):
+// block b orders chunk b - chunk_begin[t] of the table t whose chunks hold b.
+struct OrderItem {
+    const double* pos;
+    int32_t* perm;
+    OrderMap map;
+    int npos;
+    int nx, ny, nz;
+};
+struct OrderTables {
+    OrderItem t[kMaxTables];
+    int32_t chunk_begin[kMaxTables + 1];  // first chunk of each table, then the total
+    int ntables;
+};
+// Fills o with the tables of a whose perm is set; returns the total chunks.
+int64_t order_tables_config(const KernelArgs<kMaxTables>& a, OrderTables* o);
+bspl_status launch_order_tables(const OrderTables& o, hipStream_t s);
+const void* order_tables_kernel_ptr();
+unsigned order_block_threads();
+
 // Latency mode: LDS bytes a split tile's partial sums take, and the limit.
 constexpr int kSplitMaxLds = 65536;
 int64_t split_lds_bytes(int kind, int vw, int wx, int split);

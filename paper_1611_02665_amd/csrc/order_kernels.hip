@@ -38,13 +38,14 @@ __device__ __forceinline__ uint32_t bin16(double u, int n) {
     return (uint32_t)(b < 0 ? 0 : (b > 15 ? 15 : b));
 }
 
-__global__ void __launch_bounds__(kOrderThreads) order_kernel(
-    const double* __restrict__ pos, int npos, const OrderMap map, int nx, int ny, int nz,
-    int32_t* __restrict__ perm) {
+// Orders chunk `chunk` (kOrderChunk positions) of one table's positions.
+__device__ __forceinline__ void order_chunk(const double* __restrict__ pos, int npos,
+                                            const OrderMap& map, int nx, int ny, int nz,
+                                            int32_t* __restrict__ perm, int chunk) {
     __shared__ uint32_t count[kBins];
     __shared__ uint32_t wsum[kOrderThreads / 64];
     const int tid = threadIdx.x;
-    const int base = blockIdx.x * kOrderChunk;
+    const int base = chunk * kOrderChunk;
     const int cnt = min(kOrderChunk, npos - base);
     for (int b = tid; b < kBins; b += kOrderThreads) count[b] = 0u;
     __syncthreads();
@@ -106,6 +107,24 @@ __global__ void __launch_bounds__(kOrderThreads) order_kernel(
     }
 }
 
+
+__global__ void __launch_bounds__(kOrderThreads) order_kernel(
+    const double* __restrict__ pos, int npos, const OrderMap map, int nx, int ny, int nz,
+    int32_t* __restrict__ perm) {
+    order_chunk(pos, npos, map, nx, ny, nz, perm, blockIdx.x);
+}
+
+// All tables of a plan in one launch: block b belongs to the table whose
+// chunk range holds it (a scan over at most 16 offsets).
+__global__ void __launch_bounds__(kOrderThreads) order_tables_kernel(const OrderTables o) {
+    const int b = blockIdx.x;
+    int t = 0;
+    for (int k = 1; k < o.ntables; ++k)
+        if (b >= o.chunk_begin[k]) t = k;
+    const OrderItem& it = o.t[t];
+    order_chunk(it.pos, it.npos, it.map, it.nx, it.ny, it.nz, it.perm, b - o.chunk_begin[t]);
+}
+
 }  // namespace
 
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o) {
@@ -133,5 +152,45 @@ bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s) {
 }
 
 const void* order_kernel_ptr() { return (const void*)&order_kernel; }
+
+const void* order_tables_kernel_ptr() { return (const void*)&order_tables_kernel; }
+
+unsigned order_block_threads() { return kOrderThreads; }
+
+int64_t order_tables_config(const KernelArgs<kMaxTables>& a, OrderTables* o) {
+    OrderTables x{};
+    int64_t chunks = 0;
+    int n = 0;
+    for (int i = 0; i < a.ntables; ++i) {
+        const TableDesc& d = a.t[i];
+        if (!d.perm || d.npos <= 0) continue;
+        OrderItem& it = x.t[n];
+        it.pos = d.pos;
+        it.perm = const_cast<int32_t*>(d.perm);
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) it.map.m[r][c] = d.M[r][c];
+        it.npos = (int)d.npos;
+        it.nx = d.ncell[0];
+        it.ny = d.ncell[1];
+        it.nz = d.ncell[2];
+        x.chunk_begin[n] = (int32_t)chunks;
+        chunks += (d.npos + kOrderChunk - 1) / kOrderChunk;
+        ++n;
+    }
+    x.chunk_begin[n] = (int32_t)chunks;
+    x.ntables = n;
+    *o = x;
+    return chunks;
+}
+
+bspl_status launch_order_tables(const OrderTables& o, hipStream_t s) {
+    const int64_t chunks = o.chunk_begin[o.ntables];
+    if (chunks <= 0) return BSPL_OK;
+    OrderTables x = o;
+    void* args[] = {&x};
+    BSPL_HIP(hipLaunchKernel(order_tables_kernel_ptr(), dim3((unsigned)chunks),
+                             dim3(kOrderThreads), args, 0, s));
+    return BSPL_OK;
+}
 
 }  // namespace bspl
