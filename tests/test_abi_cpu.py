@@ -190,3 +190,21 @@ def test_wisdom_files(tmp_path):
     with pytest.raises(B.BsplineError) as e:
         B.spline_wisdom_save(str(tmp_path / "no" / "such" / "dir.txt"))
     assert e.value.status == B.BSPL_EIO
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the compiled library the binding refuses to import: there is
+    no CPU fallback to silently run instead."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1611_02665_amd")
+    copy = tmp_path / "paper_1611_02665_amd"
+    copy.mkdir()
+    for f in os.listdir(pkg):
+        if f.endswith(".py"):
+            shutil.copy(os.path.join(pkg, f), copy / f)
+    r = subprocess.run([sys.executable, "-c", "import paper_1611_02665_amd.binding"],
+                       cwd=tmp_path, capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libbspline.so is missing" in r.stderr
