@@ -537,6 +537,35 @@ def test_ratio_matches_oracle(kind, dtype):
         assert torch.equal(o1, o2)
 
 
+@pytest.mark.parametrize("kind", ["vgh", "vgl"])
+def test_ratio_paper_scale(paper_table, kind):
+    """Fused ratios on the 48^3 x 2048 table for all 512 positions of the
+    benchmark's first batch, at the default tile and at tiles the benchmark
+    sweeps; 64 sampled positions against the oracle's ratio sums."""
+    coef = paper_table
+    pos = synth.positions(512, stream=synth.position_stream(0))
+    rng = np.random.default_rng(21)
+    ainv = rng.standard_normal((512, 2048)).astype(np.float32)
+    idx = np.sort(rng.choice(512, 64, replace=False))
+    ref = oracle.evaluate_ratio(kind, coef.astype(np.float64), pos[:, idx],
+                                ainv[idx].astype(np.float64))
+    full = oracle.evaluate(kind, coef, pos[:, idx])
+    comps = [full["v"]] + [full["g"][:, c] for c in range(3)]
+    comps += [full["l"]] if kind == "vgl" else [full["h"][:, c] for c in range(6)]
+    scale = np.array([np.abs(x * ainv[idx]).sum(axis=1).max() for x in comps])
+    dev = torch.device("cuda")
+    pd = torch.from_numpy(pos).to(dev)
+    ad = torch.from_numpy(ainv).to(dev)
+    nc = ref.shape[1]
+    with Table(coef) as t:
+        for tile in (None, (1, 4, 1, 0, 0), (2, 8, 1, 0, 0), (4, 2, 1, 0, 0)):
+            out = torch.full((512, nc), 7.0, dtype=torch.float64, device=dev)
+            B.spline_eval_ratio(t.h, kind, 512, pd, ad, 2048, out, tile=tile)
+            torch.cuda.synchronize()
+            err = _ratio_errors(out.cpu().numpy()[idx], ref, scale)
+            assert np.all(err <= 1e-5), (tile, err)
+
+
 def test_ratio_equals_contracted_outputs(cfg1):
     """Fused ratio = host contraction of the unfused GPU outputs with ainv."""
     coef, pos, t = cfg1
