@@ -113,7 +113,9 @@ typedef struct {
  * positions, on the device, in stream-ordered scratch memory) so that
  * positions sharing table rows are evaluated together; order = 2 also hands
  * each of the 8 XCDs a contiguous run of the ordered blocks.  The order
- * changes no result: every output is computed the same way.
+ * changes no result: every output is computed the same way.  A single
+ * ordered evaluation takes its permutation from hipMallocAsync on the
+ * stream; for graph replay use a batch plan, which owns that memory.
  * split = 2 or 4 is the latency mode for a few positions (the GPU form of
  * the paper's nested threading within one walker, section "Optimizations
  * and Parallelization"): that many wavefronts share one (position, tile)
