@@ -289,7 +289,11 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     // so DEPTH groups of loads are in flight per wavefront while register use
     // stays bounded.  An empty asm that reads the partial sums of group g and
     // clobbers memory orders "reduce g" before "issue g+DEPTH"; without it the
-    // compiler hoists all 64 loads to the top and spills.
+    // compiler hoists all 64 loads to the top and spills.  The same fence
+    // after the last DEPTH groups (no loads left to order) keeps the y and x
+    // reductions incremental: otherwise the compiler defers them to the end
+    // of the slab and holds every z-sum live (FP16 VGH at VW=2 then needs 150
+    // VGPRs instead of 82).
     using RowT = Row<T, VW>;
     typename RowT::raw ring[DEPTH][4];
     auto issue = [&](int g, int slot) {
@@ -372,20 +376,18 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
                 }
             }
         }
-        if (g + DEPTH < NG) {
-            if (j == 3) {
+        if (j == 3) {
 #pragma unroll
-                for (int o = 0; o < NOUT; ++o)
+            for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) asm volatile("" : "+v"(acc[o][e]));
-            } else {
+                for (int e = 0; e < VW; ++e) asm volatile("" : "+v"(acc[o][e]));
+        } else {
 #pragma unroll
-                for (int o = 0; o < NY; ++o)
+            for (int o = 0; o < NY; ++o)
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) asm volatile("" : "+v"(Y[o][e]));
-            }
-            asm volatile("" ::: "memory");
+                for (int e = 0; e < VW; ++e) asm volatile("" : "+v"(Y[o][e]));
         }
+        asm volatile("" ::: "memory");
     }
 
     // 4a. lattice tables: grid-space derivatives to Cartesian ones,
