@@ -255,14 +255,18 @@ def main(argv=None):
                         "tile": list(tile_l.as_tuple())}
         # the same coefficients on a hexagonal cell (a general lattice: grid
         # coordinates u = M r, derivatives carried to Cartesian ones)
+        # (positions uniform in the cell: r = s A with the same s batches)
         hexcell = [[1.0, 0.0, 0.0], [-0.5, 0.75 ** 0.5, 0.0], [0.0, 0.0, 1.6]]
         thex = B.spline_table_create_lattice(*GRID, NSPL, coef, hexcell)
+        cell_t = torch.tensor(hexcell, dtype=torch.float64, device=dev).t().contiguous()
+        hex_batches = [(cell_t @ b).contiguous() for b in batches]
+        hpp = [b.data_ptr() for b in hex_batches]
         extra["lattice_hex"] = {}
         for kind, ob in (("vgh", hp), ("vgl", lp)):
             ht = B.spline_autotune(thex, kind, NPOS)
             href = B.ctypes.byref(ht)
             ms_h = timed(torch, lambda i: B._check(B.lib.spline_eval(
-                thex, B.KINDS[kind], NPOS, pp[i % nbatch], vp, gp, ob, ldo, href, stream),
+                thex, B.KINDS[kind], NPOS, hpp[i % nbatch], vp, gp, ob, ldo, href, stream),
                 "spline_eval"), max(100, steps // 2), warmup)
             extra["lattice_hex"][kind] = {
                 "evals_per_s": evals / (ms_h * 1e-3), "us_per_launch": ms_h * 1e3,
