@@ -46,7 +46,7 @@ def _random_case(rng):
     return dims, n, dtype, kind, cell, tile, npos
 
 
-@pytest.mark.parametrize("case", range(40))
+@pytest.mark.parametrize("case", range(150))
 def test_random_configuration(case):
     rng = np.random.default_rng(1000 + case)
     dims, n, dtype, kind, cell, tile, npos = _random_case(rng)
