@@ -240,7 +240,7 @@ def main(argv=None):
             "hardware": "Xeon Phi 7250P (KNL, 68 cores, MCDRAM)",
             "vgh_read_gbs": 238, "n_splines": 256,
             "implied_vgh_evals_per_s_max": 238e9 / (64 * 4),
-            "note": "SoA VGH kernel, section 'Performance Summary and Roofline analysis'"},
+            "note": "SoA VGH kernel, AoS-to-SoA subsection of the results"},
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
