@@ -245,7 +245,10 @@ bspl_status spline_eval_ratio(const bspl_table* t, bspl_kind kind, int64_t npos,
                               double* out, const bspl_tile* tile, void* stream);
 
 /* The decomposition spline_eval uses when given tile = NULL: the tuned one
- * from the wisdom cache if it holds this shape, else a built-in default.   */
+ * from the wisdom cache if it holds this shape, else a built-in default:
+ * the narrowest vector width with up to 4 spline tiles per workgroup, cell
+ * order when positions are dense (64 npos >= half the padded grid points)
+ * and npos * N >= 4M, and the latency mode (split 4) for npos <= 16.      */
 bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos,
                                bspl_tile* out);
 

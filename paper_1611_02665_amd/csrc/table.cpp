@@ -47,20 +47,32 @@ bool tile_valid(const bspl_tile& tile, int dtype) {
            tile.wx * tile.split <= 8;
 }
 
+// The decomposition used without a tuned one, from the measurements on
+// gfx950: the narrowest vector width (one 4-byte load per lane and row, the
+// fewest registers), up to 4 spline tiles per workgroup; cell order once
+// positions are dense enough to share rows (64 npos / padded points >= 1/2)
+// and the work amortises the ordering pass (npos * N >= 4M); and for a
+// handful of positions the latency mode with 4 wavefronts per unit.
 bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos) {
     (void)kind;
-    (void)npos;
     const int64_t n = t->info.n_splines;
     bspl_tile tile{};
-    if (t->info.dtype == BSPL_F32)
-        tile.vw = n >= 256 ? 4 : (n >= 128 ? 2 : 1);
-    else
-        tile.vw = n >= 512 ? 8 : (n >= 256 ? 4 : 2);
+    tile.vw = t->info.dtype == BSPL_F32 ? 1 : 2;
     const int64_t chunks = (n + 64 * tile.vw - 1) / (64 * tile.vw);
-    tile.wx = (int)std::min<int64_t>(4, chunks);
-    tile.wy = std::max(1, 4 / tile.wx);
     tile.grid = 0;
     tile.order = 0;
+    if (npos <= 16) {  // split * wx * n_out * vw * 256 B <= 20 KiB of LDS
+        tile.wx = 1;
+        tile.wy = 1;
+        tile.split = 4;
+        return tile;
+    }
+    tile.wx = (int)std::min<int64_t>(4, chunks);
+    tile.wy = 1;
+    tile.split = 1;
+    const double points = (double)t->info.px * t->info.py * t->info.pz;
+    if (64.0 * (double)npos >= 0.5 * points && (double)npos * (double)n >= 4194304.0)
+        tile.order = 1;
     return tile;
 }
 
@@ -431,9 +443,15 @@ bspl_status spline_eval_ratio(const bspl_table* t, bspl_kind kind, int64_t npos,
             return fail(BSPL_EINVAL, "tile invalid for dtype %d", t->info.dtype);
         if (tl.split > 1) return fail(BSPL_EINVAL, "split tiles are for evaluations only");
     } else {
+        // two splines per lane and up to 8 wavefronts per position measured
+        // best for the ratio kernel on gfx950 (valid for every dtype)
         tl = default_tile(t, kind, npos);
+        tl.vw = 2;
         const int64_t chunks = (t->info.n_splines + 64 * tl.vw - 1) / (64 * tl.vw);
         tl.wx = (int)std::min<int64_t>(8, chunks);
+        tl.wy = 1;
+        tl.order = 0;
+        tl.split = 1;
     }
     TableDesc d;
     bspl_status st = make_desc(t, npos, pos, nullptr, nullptr, nullptr, t->info.n_splines, tl.vw,
