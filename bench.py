@@ -624,6 +624,19 @@ def sweep_mode(torch, B, A, synth):
                                           "us_per_launch": ms * 1e3,
                                           "evals_per_s": npos * n / (ms * 1e-3)}), flush=True)
         B.spline_table_destroy(t)
+        # the same table stored as FP16 (per-spline scales), VGH
+        coef = synth.coef_table(*GRID, n, stream=synth.table_stream(0))
+        t16 = B.spline_table_create(*GRID, n, coef, "f16")
+        del coef
+        tile = B.spline_autotune(t16, "vgh", npos)
+        ms = timed(torch, lambda i: B.spline_eval(t16, "vgh", npos, batches[i % NBATCH], v, g, h,
+                                                  n, stream=stream), 200, 20)
+        print(json.dumps({"sweep": "n_splines", "grid": list(GRID), "n_splines": n,
+                          "npos": npos, "kernel": "eval_vgh", "table_dtype": "f16",
+                          "us_per_launch": ms * 1e3, "evals_per_s": npos * n / (ms * 1e-3),
+                          "hbm_gbs": A.batch_bytes("vgh", "f16", npos, n) / (ms * 1e-3) / 1e9,
+                          "tile": list(tile.as_tuple())}), flush=True)
+        B.spline_table_destroy(t16)
         del v, g, h
         torch.cuda.empty_cache()
     return 0
