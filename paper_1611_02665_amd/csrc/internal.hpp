@@ -95,17 +95,18 @@ const void* multi_kernel_ptr(int dtype, int kind, int vw, int lattice);
 // Cell-ordering pre-pass (order_kernels.hip): perm[i] for i < npos.
 // OrderLaunch holds the launch shape and the argument values (args[] points
 // into the struct, so it must not be copied after order_launch_config).
+// OrderMap takes a Cartesian position to its fractional cell coordinates
+// (grid coordinates divided by the cell counts, period 1 on every axis).
 struct OrderMap {
-    double m[3][3];
+    double f[3][3];
 };
 struct OrderLaunch {
     const double* pos;
     int npos;
     OrderMap map;
-    int nx, ny, nz;
     int32_t* perm;
     unsigned grid, block, shmem;
-    void* args[7];
+    void* args[4];
 };
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o);
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s);
@@ -117,7 +118,6 @@ struct OrderItem {
     int32_t* perm;
     OrderMap map;
     int npos;
-    int nx, ny, nz;
 };
 struct OrderTables {
     OrderItem t[kMaxTables];

@@ -29,19 +29,28 @@ __device__ __forceinline__ uint32_t spread3_4(uint32_t v) {  // 4 bits -> every 
     return v;
 }
 
-// Bin coordinate (0..15) of grid coordinate u on a periodic axis of n cells.
-__device__ __forceinline__ uint32_t bin16(double u, int n) {
-    if (!__builtin_isfinite(u) || !(__builtin_fabs(u) < 1125899906842624.0)) return 0u;
-    const double nd = (double)n;
-    const double w = u - nd * __builtin_floor(u / nd);
-    int b = (int)(w * (16.0 / nd));
-    return (uint32_t)(b < 0 ? 0 : (b > 15 ? 15 : b));
+// Bin coordinate (0..15) of fractional coordinate t on a periodic axis:
+// the fraction of t times 16.  The bin only steers the order (any bin is a
+// valid answer), so a multiply by 1/n precomputed on the host stands in for
+// the division by n, and non-finite or huge coordinates share bin 0.
+__device__ __forceinline__ uint32_t bin16(double t) {
+    if (!(__builtin_fabs(t) < 1125899906842624.0)) return 0u;  // NaN, inf, |t| >= 2^50
+    const int b = (int)((t - __builtin_floor(t)) * 16.0);
+    return (uint32_t)(b > 15 ? 15 : b);
+}
+
+// Fractional coordinates of position p: the map's rows times (x, y, z).
+__device__ __forceinline__ uint32_t morton_bin(const OrderMap& map, double x, double y, double z) {
+    const uint32_t bx = bin16(map.f[0][0] * x + map.f[0][1] * y + map.f[0][2] * z);
+    const uint32_t by = bin16(map.f[1][0] * x + map.f[1][1] * y + map.f[1][2] * z);
+    const uint32_t bz = bin16(map.f[2][0] * x + map.f[2][1] * y + map.f[2][2] * z);
+    return (spread3_4(bx) << 2) | (spread3_4(by) << 1) | spread3_4(bz);
 }
 
 // Orders chunk `chunk` (kOrderChunk positions) of one table's positions.
 __device__ __forceinline__ void order_chunk(const double* __restrict__ pos, int npos,
-                                            const OrderMap& map, int nx, int ny, int nz,
-                                            int32_t* __restrict__ perm, int chunk) {
+                                            const OrderMap& map, int32_t* __restrict__ perm,
+                                            int chunk) {
     __shared__ uint32_t count[kBins];
     __shared__ uint32_t wsum[kOrderThreads / 64];
     const int tid = threadIdx.x;
@@ -58,12 +67,7 @@ __device__ __forceinline__ void order_chunk(const double* __restrict__ pos, int 
         bin[r] = 0u;
         if (i < cnt) {
             const int p = base + i;
-            const double x = pos[p], y = pos[(int64_t)npos + p], z = pos[2 * (int64_t)npos + p];
-            const double* m = &map.m[0][0];
-            const uint32_t bx = bin16(m[0] * x + m[1] * y + m[2] * z, nx);
-            const uint32_t by = bin16(m[3] * x + m[4] * y + m[5] * z, ny);
-            const uint32_t bz = bin16(m[6] * x + m[7] * y + m[8] * z, nz);
-            bin[r] = (spread3_4(bx) << 2) | (spread3_4(by) << 1) | spread3_4(bz);
+            bin[r] = morton_bin(map, pos[p], pos[(int64_t)npos + p], pos[2 * (int64_t)npos + p]);
         }
     }
 #pragma unroll
@@ -109,9 +113,8 @@ __device__ __forceinline__ void order_chunk(const double* __restrict__ pos, int 
 
 
 __global__ void __launch_bounds__(kOrderThreads) order_kernel(
-    const double* __restrict__ pos, int npos, const OrderMap map, int nx, int ny, int nz,
-    int32_t* __restrict__ perm) {
-    order_chunk(pos, npos, map, nx, ny, nz, perm, blockIdx.x);
+    const double* __restrict__ pos, int npos, const OrderMap map, int32_t* __restrict__ perm) {
+    order_chunk(pos, npos, map, perm, blockIdx.x);
 }
 
 // All tables of a plan in one launch: block b belongs to the table whose
@@ -122,25 +125,29 @@ __global__ void __launch_bounds__(kOrderThreads) order_tables_kernel(const Order
     for (int k = 1; k < o.ntables; ++k)
         if (b >= o.chunk_begin[k]) t = k;
     const OrderItem& it = o.t[t];
-    order_chunk(it.pos, it.npos, it.map, it.nx, it.ny, it.nz, it.perm, b - o.chunk_begin[t]);
+    order_chunk(it.pos, it.npos, it.map, it.perm, b - o.chunk_begin[t]);
 }
 
 }  // namespace
 
+// Fractional-coordinate map of a table: row a of the grid map over n_a.
+static OrderMap fraction_map(const TableDesc& d) {
+    OrderMap m;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) m.f[a][b] = d.M[a][b] / (double)d.ncell[a];
+    return m;
+}
+
 void order_launch_config(const TableDesc& d, int32_t* perm, OrderLaunch* o) {
     o->pos = d.pos;
     o->npos = (int)d.npos;
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) o->map.m[a][b] = d.M[a][b];
-    o->nx = d.ncell[0];
-    o->ny = d.ncell[1];
-    o->nz = d.ncell[2];
+    o->map = fraction_map(d);
     o->perm = perm;
     o->grid = (unsigned)((d.npos + kOrderChunk - 1) / kOrderChunk);
     o->block = kOrderThreads;
     o->shmem = 0;
-    void* a[] = {&o->pos, &o->npos, &o->map, &o->nx, &o->ny, &o->nz, &o->perm};
-    for (int i = 0; i < 7; ++i) o->args[i] = a[i];
+    void* a[] = {&o->pos, &o->npos, &o->map, &o->perm};
+    for (int i = 0; i < 4; ++i) o->args[i] = a[i];
 }
 
 bspl_status launch_order(const TableDesc& d, int32_t* perm, hipStream_t s) {
@@ -167,12 +174,8 @@ int64_t order_tables_config(const KernelArgs<kMaxTables>& a, OrderTables* o) {
         OrderItem& it = x.t[n];
         it.pos = d.pos;
         it.perm = const_cast<int32_t*>(d.perm);
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) it.map.m[r][c] = d.M[r][c];
+        it.map = fraction_map(d);
         it.npos = (int)d.npos;
-        it.nx = d.ncell[0];
-        it.ny = d.ncell[1];
-        it.nz = d.ncell[2];
         x.chunk_begin[n] = (int32_t)chunks;
         chunks += (d.npos + kOrderChunk - 1) / kOrderChunk;
         ++n;
