@@ -124,3 +124,52 @@ def test_plan_with_sixteen_tables():
     finally:
         for h in hs:
             B.spline_table_destroy(h)
+
+
+def _degenerate_position_sets(cell):
+    """Position sets that stress the ordering pre-pass's counting sort:
+    every position in one bin (two chunks, ragged tail), grid points and
+    bin boundaries with far periodic images, two tight clusters, and
+    non-finite coordinates (which all share bin 0)."""
+    rng = np.random.default_rng(190)
+    same = np.tile(np.array([[0.37], [0.52], [0.91]]), (1, 5000))
+    k = np.arange(4200)
+    grid_pts = np.stack([(k % 16) / 16.0, ((k // 16) % 16) / 16.0, (k // 256) / 16.0])
+    grid_pts = grid_pts + rng.integers(-10**6, 10**6, (3, 1)) * np.array([[1.0], [-1.0], [1.0]])
+    grid_pts[:, ::7] *= -1.0
+    clusters = np.concatenate([0.2 + 1e-6 * rng.standard_normal((3, 2100)),
+                               0.8 + 1e-6 * rng.standard_normal((3, 2100))], axis=1)
+    mixed = rng.uniform(-3.0, 4.0, (3, 4500))
+    mixed[0, ::11] = np.nan
+    mixed[1, 5::13] = np.inf
+    mixed[2, 7::17] = -np.inf
+    with np.errstate(invalid="ignore"):  # inf * 0 in the map: that position stays non-finite
+        return {name: np.ascontiguousarray(cell.T @ f) for name, f in
+                (("one bin", same), ("grid points", grid_pts), ("clusters", clusters),
+                 ("non-finite", mixed))}
+
+
+@pytest.mark.parametrize("cell", ["box", "hex"])
+def test_ordering_degenerate_distributions(cell):
+    """Orders 1 and 2 give the same bits as input order on position sets that
+    pile every position into one bin or sit on bin boundaries; a position
+    the permutation dropped would keep its canary and fail the comparison."""
+    coef = synth.coef_table(9, 10, 11, 130, stream=191)
+    A = np.eye(3) if cell == "box" else HEX
+    h = B.spline_table_create_lattice(9, 10, 11, 130, coef, A, "f32")
+    try:
+        for name, pos in _degenerate_position_sets(A).items():
+            for kind in ("v", "vgh"):
+                outs = [run_gpu(B, h, kind, pos, 130, tile=(1, 2, 1, 0, order, 1))[1]
+                        for order in (0, 1, 2)]
+                for o in outs[1:]:
+                    for key in o:
+                        assert np.array_equal(o[key], outs[0][key], equal_nan=True), \
+                            (cell, name, kind, key)
+                assert not np.any(outs[0]["v"][:, :130] == 12345.0), (cell, name, kind)
+        finite = _degenerate_position_sets(A)["grid points"][:, :64]
+        gpu, _ = run_gpu(B, h, "vgh", finite, 130, tile=(1, 2, 1, 0, 1, 1))
+        assert_close("vgh", gpu, oracle.evaluate_lattice("vgh", coef, finite, A),
+                     label=f"{cell} grid points, ordered")
+    finally:
+        B.spline_table_destroy(h)
