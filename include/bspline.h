@@ -76,16 +76,27 @@ typedef enum { BSPL_V = 0, BSPL_VGL = 1, BSPL_VGH = 2 } bspl_kind;
 #define BSPL_COEFS_GRID_VALUES 0x4u /* coefs are orbital values at the grid
                                        points; the table gets the interpolating
                                        coefficients (spline_fit_interpolating) */
+#define BSPL_LAYOUT_BLOCKED 0x8u    /* store the table spline-blocked (see
+                                       bspl_table_info); evaluation results are
+                                       bit-identical to the plain layout      */
 
 typedef struct bspl_table bspl_table;
 typedef struct bspl_plan bspl_plan;
 
-/* Layout of a table in device memory.  The table is 4-D,
+/* Layout of a table in device memory.  The plain table is 4-D,
  * [nx+3][ny+3][nz+3][n_padded]: one row of n_padded coefficients per padded
  * grid point, n fastest, each row starting on a 128-byte boundary (paper:
  * coefficient array P[Nx][Ny][Nz][N] with aligned, padded rows, section
  * "Baseline and miniQMC").  Padded index i holds the periodic coefficient
- * (i-1) mod n, so the 4 rows a cell needs are always i0..i0+3.            */
+ * (i-1) mod n, so the 4 rows a cell needs are always i0..i0+3.
+ * The spline-blocked table (BSPL_LAYOUT_BLOCKED; the paper's AoSoA table,
+ * an array of sub-tables of N_b splines each, section "Optimizations and
+ * Parallelization") is 5-D, [n_padded / B][nx+3][ny+3][nz+3][B] with
+ * B = block_splines = 256 (F32) or 512 (F16/BF16), the widest spline tile,
+ * so that the 4 z rows of a cell within one block are contiguous (a row of
+ * B elements is 1 KB).  A spline tile of 64*vw splines always lies in one
+ * block.  A table of at most B splines is a single block, which is the
+ * plain layout (block_splines = 0).                                        */
 typedef struct {
     int32_t nx, ny, nz;       /* grid cells per dimension */
     int32_t px, py, pz;       /* padded points per dimension (n + 3) */
@@ -93,12 +104,15 @@ typedef struct {
     int64_t n_padded;         /* row length in elements (multiple of 128 B) */
     int32_t dtype;            /* bspl_dtype */
     int32_t elem_bytes;       /* 4 or 2 */
-    int64_t row_bytes;        /* n_padded * elem_bytes */
+    int64_t row_bytes;        /* bytes between consecutive z rows: n_padded *
+                                 elem_bytes (plain) or block_splines * elem_bytes */
     int64_t table_bytes;      /* px*py*pz*row_bytes */
     double box[3];            /* cell vector lengths (the box of an orthorhombic cell) */
     double lattice[9];        /* cell vectors a1, a2, a3 as rows (Cartesian) */
     const void* data;         /* device pointer to the table (read-only) */
     const float* scales;      /* device pointer to n_padded scales, or NULL */
+    int64_t block_splines;    /* splines per block (spline-blocked), or 0 (plain) */
+    int64_t block_bytes;      /* bytes of one block (spline-blocked), or 0 (plain) */
 } bspl_table_info;
 
 /* Work decomposition of one evaluation.  A wavefront (64 lanes) handles one
@@ -142,11 +156,12 @@ const char* spline_status_string(bspl_status s);
 const char* spline_last_error(void);
 
 /* Host-only layout query: fills *out (data and scales set to NULL) for the
- * given shape without touching the device.  EINVAL for non-positive sizes
- * or a bad dtype; EUNSUPPORTED when a size overflows 64-bit byte counts or
- * the 4x4x4 row block of one cell spans 4 GiB or more.                   */
+ * given shape and layout flag (0 or BSPL_LAYOUT_BLOCKED; other creation
+ * flags are ignored) without touching the device.  EINVAL for non-positive
+ * sizes or a bad dtype; EUNSUPPORTED when a size overflows 64-bit byte
+ * counts or the 4x4x4 row block of one cell spans 4 GiB or more.         */
 bspl_status spline_layout_query(int nx, int ny, int nz, int64_t n_splines,
-                                bspl_dtype dtype, bspl_table_info* out);
+                                bspl_dtype dtype, unsigned flags, bspl_table_info* out);
 
 /* Create a table from FP32 coefficients.
  *  coefs: [nx][ny][nz][n_splines], n fastest, periodic (the coefficient of
@@ -154,6 +169,9 @@ bspl_status spline_layout_query(int nx, int ny, int nz, int64_t n_splines,
  *         with BSPL_COEFS_DEVICE; with BSPL_COEFS_PADDED the array is
  *         [nx+3][ny+3][nz+3][n_splines] and padded index i is used for
  *         cell i-1 directly (no periodic fill).
+ *  flags: BSPL_COEFS_* as above, plus BSPL_LAYOUT_BLOCKED for the
+ *         spline-blocked layout (spline_layout_select measures which layout
+ *         is faster for a shape).
  *  box:   three box lengths (> 0), or NULL for the unit cube.
  *  The library copies, pads, converts and owns the table.  The call
  *  returns when the table is ready on the device; coefs may be freed then.
@@ -262,12 +280,31 @@ bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos
 bspl_status spline_autotune(const bspl_table* t, bspl_kind kind, int64_t npos,
                             const char* wisdom_path, bspl_tile* best, void* stream);
 
+/* Layout selection (the paper tunes the AoSoA sub-table size with the tile
+ * size, section "Experiments and Results").  Decides between the plain and
+ * the spline-blocked layout for tables of this shape, dtype and kind at
+ * this batch size, on box cells, and returns 0 or BSPL_LAYOUT_BLOCKED in
+ * *layout.  It compares the best tile times that the wisdom cache holds
+ * for both layouts; a layout without a timed entry is autotuned on a
+ * temporary zero-coefficient table of the real shape (timing does not
+ * depend on the values), which is recorded in the cache and appended to
+ * wisdom_path when that is not NULL.  Shapes of at most one block
+ * (n_splines <= 256 for F32, 512 for F16/BF16) return 0 at once.  Needs
+ * device memory for one table of each layout plus the unpadded
+ * coefficients; synchronizes the stream.  Errors as spline_table_create
+ * and spline_autotune.                                                    */
+bspl_status spline_layout_select(int nx, int ny, int nz, int64_t n_splines, bspl_dtype dtype,
+                                 bspl_kind kind, int64_t npos, const char* wisdom_path,
+                                 unsigned* layout, void* stream);
+
 /* Load wisdom entries from a file into the cache (EIO if unreadable).  One
  * entry per line: "key vw wx wy grid order split [time_us]"; other lines
- * (comments, older formats) are skipped.                                 */
+ * (comments, older formats) are skipped.  Keys of spline-blocked tables
+ * carry "-blocked" in their first field.                                  */
 bspl_status spline_wisdom_load(const char* path);
 
-/* Write the whole wisdom cache to a file (EIO on failure). */
+/* Write the whole wisdom cache to a file, with the tile times it holds
+ * (EIO on failure). */
 bspl_status spline_wisdom_save(const char* path);
 
 /* Batched evaluation of several tables in one kernel launch (a grid that

@@ -30,6 +30,7 @@ BSPL_V, BSPL_VGL, BSPL_VGH = 0, 1, 2
 BSPL_COEFS_PADDED = 0x1
 BSPL_COEFS_DEVICE = 0x2
 BSPL_COEFS_GRID_VALUES = 0x4
+BSPL_LAYOUT_BLOCKED = 0x8
 MAX_TABLES = 16
 
 DTYPES = {"f32": BSPL_F32, "f16": BSPL_F16, "bf16": BSPL_BF16}
@@ -45,7 +46,8 @@ class bspl_table_info(ctypes.Structure):
                 ("row_bytes", ctypes.c_int64), ("table_bytes", ctypes.c_int64),
                 ("box", ctypes.c_double * 3), ("lattice", ctypes.c_double * 9),
                 ("data", ctypes.c_void_p),
-                ("scales", ctypes.c_void_p)]
+                ("scales", ctypes.c_void_p),
+                ("block_splines", ctypes.c_int64), ("block_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,7 +75,10 @@ _P = ctypes.POINTER
 _SIGS = {
     "spline_status_string": (ctypes.c_char_p, [_int]),
     "spline_last_error": (ctypes.c_char_p, []),
-    "spline_layout_query": (_int, [_int, _int, _int, _i64, _int, _P(bspl_table_info)]),
+    "spline_layout_query": (_int, [_int, _int, _int, _i64, _int, ctypes.c_uint,
+                                   _P(bspl_table_info)]),
+    "spline_layout_select": (_int, [_int, _int, _int, _i64, _int, _int, _i64, ctypes.c_char_p,
+                                    _P(ctypes.c_uint), _vp]),
     "spline_table_create": (_int, [_P(_vp), _int, _int, _int, _i64, _vp, _int,
                                    _P(ctypes.c_double), _u32, _vp]),
     "spline_fit_interpolating": (_int, [_int, _int, _int, _i64, _vp, _vp, _vp]),
@@ -153,11 +158,22 @@ def spline_last_error() -> str:
     return lib.spline_last_error().decode()
 
 
-def spline_layout_query(nx, ny, nz, n_splines, dtype="f32") -> dict:
+def spline_layout_query(nx, ny, nz, n_splines, dtype="f32", flags=0) -> dict:
     info = bspl_table_info()
-    _check(lib.spline_layout_query(nx, ny, nz, n_splines, _enum(dtype, DTYPES),
+    _check(lib.spline_layout_query(nx, ny, nz, n_splines, _enum(dtype, DTYPES), flags,
                                    ctypes.byref(info)), "spline_layout_query")
     return info.as_dict()
+
+
+def spline_layout_select(nx, ny, nz, n_splines, dtype, kind, npos, wisdom_path=None,
+                         stream=None) -> int:
+    """0 (plain) or BSPL_LAYOUT_BLOCKED, whichever runs this shape faster."""
+    out = ctypes.c_uint(0)
+    wp = wisdom_path.encode() if wisdom_path else None
+    _check(lib.spline_layout_select(nx, ny, nz, n_splines, _enum(dtype, DTYPES),
+                                    _enum(kind, KINDS), npos, wp, ctypes.byref(out),
+                                    _stream(stream)), "spline_layout_select")
+    return out.value
 
 
 def spline_table_create(nx, ny, nz, n_splines, coefs, dtype="f32", box=None, flags=0,

@@ -21,9 +21,15 @@ namespace bspl {
 
 namespace {
 
+// A cached decision: the tile, and its measured time when known (< 0 if not).
+struct Entry {
+    bspl_tile tile;
+    float us;
+};
+
 std::mutex g_mu;
-std::map<std::string, bspl_tile>& cache() {
-    static std::map<std::string, bspl_tile> c;
+std::map<std::string, Entry>& cache() {
+    static std::map<std::string, Entry> c;
     return c;
 }
 
@@ -52,15 +58,17 @@ int64_t pow2_bucket(int64_t n) {
     return b;
 }
 
-bool parse_line(const char* line, std::string* key, bspl_tile* t) {
+bool parse_line(const char* line, std::string* key, bspl_tile* t, float* us) {
     char k[256];
     bspl_tile x{};
+    float time_us = -1.f;
     // key vw wx wy grid order split [time_us]
-    if (sscanf(line, "%255s %d %d %d %d %d %d", k, &x.vw, &x.wx, &x.wy, &x.grid, &x.order,
-               &x.split) != 7)
-        return false;
+    const int n = sscanf(line, "%255s %d %d %d %d %d %d %f", k, &x.vw, &x.wx, &x.wy, &x.grid,
+                         &x.order, &x.split, &time_us);
+    if (n < 7) return false;
     *key = k;
     *t = x;
+    *us = n == 8 ? time_us : -1.f;
     return true;
 }
 
@@ -89,17 +97,23 @@ void wisdom_key(char* buf, size_t n, int dtype, int kind, int64_t nsplines, cons
              (long long)pow2_bucket(npos));
 }
 
-bool wisdom_lookup(const char* key, bspl_tile* out) {
+void key_prefix(char* buf, size_t n, const char* base, const bspl_table* t) {
+    snprintf(buf, n, "%s%s%s", base, t->lattice ? "-lattice" : "",
+             t->info.block_splines ? "-blocked" : "");
+}
+
+bool wisdom_lookup(const char* key, bspl_tile* out, float* us) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = cache().find(key);
     if (it == cache().end()) return false;
-    *out = it->second;
+    *out = it->second.tile;
+    if (us) *us = it->second.us;
     return true;
 }
 
-void wisdom_store(const char* key, const bspl_tile& tile) {
+void wisdom_store(const char* key, const bspl_tile& tile, float us) {
     std::lock_guard<std::mutex> lk(g_mu);
-    cache()[key] = tile;
+    cache()[key] = Entry{tile, us};
 }
 
 // Candidate decompositions for a table (and, for batched launches, grid
@@ -215,7 +229,7 @@ static bspl_status append_wisdom(const char* path, const char* key, const bspl_t
 }
 
 bspl_status record_wisdom(const char* path, const char* key, const bspl_tile& t, float us) {
-    wisdom_store(key, t);
+    wisdom_store(key, t, us);
     return path ? append_wisdom(path, key, t, us) : BSPL_OK;
 }
 
@@ -284,13 +298,68 @@ bspl_status spline_autotune(const bspl_table* t, bspl_kind kind, int64_t npos,
     (void)hipStreamSynchronize(s);
     (void)hipFree(mem);
     if (st != BSPL_OK) return st;
-    char key[256];
+    char key[256], prefix[64];
     const int32_t nc[3] = {t->info.nx, t->info.ny, t->info.nz};
-    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos,
-               t->lattice ? "single-lattice" : "single");
+    key_prefix(prefix, sizeof prefix, "single", t);
+    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos, prefix);
     st = record_wisdom(wisdom_path, key, bt, us);
     if (best) *best = bt;
     return st;
+}
+
+bspl_status spline_layout_select(int nx, int ny, int nz, int64_t n_splines, bspl_dtype dtype,
+                                 bspl_kind kind, int64_t npos, const char* wisdom_path,
+                                 unsigned* layout, void* stream) {
+    if (!layout) return fail(BSPL_EINVAL, "layout is NULL");
+    *layout = 0;
+    if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
+    if (npos <= 0 || npos > INT32_MAX) return fail(BSPL_EINVAL, "npos %lld", (long long)npos);
+    bspl_table_info info{};
+    bspl_status st = spline_layout_query(nx, ny, nz, n_splines, dtype, BSPL_LAYOUT_BLOCKED, &info);
+    if (st != BSPL_OK) return st;
+    if (info.block_splines == 0) return BSPL_OK;  // one block: the layouts coincide
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t nc[3] = {nx, ny, nz};
+    const unsigned flags[2] = {0u, BSPL_LAYOUT_BLOCKED};
+    const char* prefixes[2] = {"single", "single-blocked"};
+    float best[2] = {-1.f, -1.f};
+    float* zeros = nullptr;
+    for (int l = 0; l < 2 && st == BSPL_OK; ++l) {
+        char key[256];
+        wisdom_key(key, sizeof key, dtype, kind, n_splines, nc, npos, prefixes[l]);
+        bspl_tile tile;
+        float us = -1.f;
+        if (wisdom_lookup(key, &tile, &us) && us > 0.f) {
+            best[l] = us;
+            continue;
+        }
+        // tune this layout on a temporary table of the real shape
+        const size_t elems = (size_t)nx * ny * nz * (size_t)n_splines;
+        if (!zeros) {
+            hipError_t e = hipMalloc((void**)&zeros, sizeof(float) * elems);
+            if (e == hipSuccess) e = hipMemsetAsync(zeros, 0, sizeof(float) * elems, s);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "layout selection coefficients");
+                break;
+            }
+        }
+        bspl_table* t = nullptr;
+        st = spline_table_create(&t, nx, ny, nz, n_splines, zeros, dtype, nullptr,
+                                 BSPL_COEFS_DEVICE | flags[l], stream);
+        if (st != BSPL_OK) break;
+        st = spline_autotune(t, kind, npos, wisdom_path, nullptr, stream);
+        spline_table_destroy(t);
+        if (st == BSPL_OK && !(wisdom_lookup(key, &tile, &us) && us > 0.f))
+            st = fail(BSPL_EDEVICE, "layout selection found no timing for %s", key);
+        best[l] = us;
+    }
+    if (zeros) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(zeros);
+    }
+    if (st != BSPL_OK) return st;
+    *layout = best[1] < best[0] ? BSPL_LAYOUT_BLOCKED : 0u;
+    return BSPL_OK;
 }
 
 bspl_status spline_wisdom_load(const char* path) {
@@ -301,8 +370,9 @@ bspl_status spline_wisdom_load(const char* path) {
     while (fgets(line, sizeof line, f)) {
         std::string key;
         bspl_tile tile;
-        if (line[0] == '#' || !parse_line(line, &key, &tile)) continue;
-        wisdom_store(key.c_str(), tile);
+        float us = -1.f;
+        if (line[0] == '#' || !parse_line(line, &key, &tile, &us)) continue;
+        wisdom_store(key.c_str(), tile, us);
     }
     fclose(f);
     return BSPL_OK;
@@ -314,9 +384,13 @@ bspl_status spline_wisdom_save(const char* path) {
     if (!f) return fail(BSPL_EIO, "cannot create wisdom file %s", path);
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        for (auto& kv : cache())
-            fprintf(f, "%s %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.vw, kv.second.wx,
-                    kv.second.wy, kv.second.grid, kv.second.order, kv.second.split);
+        for (auto& kv : cache()) {
+            const bspl_tile& t = kv.second.tile;
+            fprintf(f, "%s %d %d %d %d %d %d", kv.first.c_str(), t.vw, t.wx, t.wy, t.grid,
+                    t.order, t.split);
+            if (kv.second.us > 0.f) fprintf(f, " %.3f", kv.second.us);
+            fputc('\n', f);
+        }
     }
     return fclose(f) == 0 ? BSPL_OK : fail(BSPL_EIO, "cannot write wisdom file %s", path);
 }

@@ -103,8 +103,11 @@ void batch_key(const bspl_plan& p, char* buf, size_t n) {
         char part[256];
         const bspl_table_info& in = p.tables[i]->info;
         const int32_t nc[3] = {in.nx, in.ny, in.nz};
-        wisdom_key(part, sizeof part, in.dtype, p.kind, in.n_splines, nc, p.npos[i],
-                   i == 0 ? (plan_lattice(p) ? "batch-lattice" : "batch") : "");
+        char prefix[64];
+        snprintf(prefix, sizeof prefix, "%s%s",
+                 i == 0 ? (plan_lattice(p) ? "batch-lattice" : "batch") : "",
+                 in.block_splines ? "-blocked" : "");
+        wisdom_key(part, sizeof part, in.dtype, p.kind, in.n_splines, nc, p.npos[i], prefix);
         k += (i == 0 ? "" : "+");
         k += part;
     }

@@ -280,8 +280,16 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     // 3. gather and reduce
     const int n0 = chunk * (64 * VW) + lane * VW;
     const int valid = d.nsplines - n0;  // > 0 for lanes that own splines
+    // the tile's columns: plain rows hold every spline; a spline-blocked
+    // table holds chunks_per_block tiles per block (chunk is wave-uniform)
+    size_t tile_off = (size_t)chunk * (64 * VW * EB);
+    if (d.block_bytes) {
+        const int blk = chunk / d.chunks_per_block;
+        tile_off = (size_t)blk * (size_t)d.block_bytes +
+                   (size_t)(chunk - blk * d.chunks_per_block) * (64 * VW * EB);
+    }
     const char* base = d.table + (size_t)(i0 + islab) * d.xstride + (size_t)j0 * d.ystride +
-                       (size_t)k0 * d.row_bytes + (size_t)chunk * (64 * VW * EB);
+                       (size_t)k0 * d.row_bytes + tile_off;
     const uint32_t loff = valid > 0 ? (uint32_t)(lane * VW * EB) : 0u;
 
     // Row groups g = 4i + j (16 of them, 4 z-rows each) stream through a ring

@@ -25,6 +25,10 @@ constexpr int kMaxTables = 16;
 constexpr int kOrderChunk = 4096;
 // XCDs of an MI355X; workgroups are dispatched to them round-robin.
 constexpr int kXcds = 8;
+// Splines per block of a spline-blocked table: the widest spline tile
+// (64 lanes times the largest vector width of the dtype), so that every
+// tile lies in one block.
+inline int64_t block_splines_of(int dtype) { return dtype == BSPL_F32 ? 256 : 512; }
 
 // Record a failure message for spline_last_error() and return the status.
 bspl_status fail(bspl_status s, const char* fmt, ...);
@@ -58,6 +62,8 @@ struct TableDesc {
     uint32_t row_bytes;       // bytes between consecutive z rows
     uint32_t ystride;         // bytes between consecutive y planes
     uint32_t xstride;         // bytes between consecutive x planes
+    int64_t block_bytes;      // spline-blocked tables: bytes per block; plain: 0
+    int32_t chunks_per_block; // spline tiles of 64*vw per block (plain: nchunks)
     int32_t nsplines;
     int32_t nchunks;          // spline tiles of 64*vw covering nsplines
     int32_t xgroups;          // blocks along splines: ceil(nchunks / wx)
@@ -145,8 +151,13 @@ bspl_status build_table(bspl_table* t, const float* d_coefs, bool padded_input,
                         hipStream_t s);
 
 // Wisdom cache (autotune.cpp).
-bool wisdom_lookup(const char* key, bspl_tile* out);
-void wisdom_store(const char* key, const bspl_tile& tile);
+// Entries keep the tile and its measured time in microseconds (< 0 when a
+// wisdom line carried none).
+bool wisdom_lookup(const char* key, bspl_tile* out, float* us = nullptr);
+void wisdom_store(const char* key, const bspl_tile& tile, float us = -1.f);
+// Key prefix of a table: base, then "-lattice" for a general cell and
+// "-blocked" for the spline-blocked layout.
+void key_prefix(char* buf, size_t n, const char* base, const bspl_table* t);
 void wisdom_key(char* buf, size_t n, int dtype, int kind, int64_t nsplines,
                 const int32_t ncell[3], int64_t npos, const char* prefix);
 

@@ -54,10 +54,12 @@ __device__ __forceinline__ uint16_t to_bf16_rne(float x) {
     return (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
 }
 
+// Element n of padded point pt goes to block n / bs at row pt, column
+// n % bs: [np / bs][px][py][pz][bs].  The plain layout is bs = np.
 template <int DT>
 __global__ void pad_kernel(const float* __restrict__ c, int padded_in, int nx, int ny, int nz,
-                           int64_t nsplines, int64_t np, const float* __restrict__ scales,
-                           void* __restrict__ out) {
+                           int64_t nsplines, int64_t np, int64_t bs,
+                           const float* __restrict__ scales, void* __restrict__ out) {
     const int px = nx + 3, py = ny + 3, pz = nz + 3;
     const int64_t npts = (int64_t)px * py * pz;
     for (int64_t pt = blockIdx.x; pt < npts; pt += gridDim.x) {
@@ -74,7 +76,8 @@ __global__ void pad_kernel(const float* __restrict__ c, int padded_in, int nx, i
         const float* row = c + src * nsplines;
         for (int64_t n = threadIdx.x; n < np; n += blockDim.x) {
             const float x = n < nsplines ? row[n] : 0.f;
-            const int64_t o = pt * np + n;
+            const int64_t blk = n / bs;
+            const int64_t o = blk * npts * bs + pt * bs + (n - blk * bs);
             if constexpr (DT == BSPL_F32) {
                 static_cast<float*>(out)[o] = x;
             } else {
@@ -109,20 +112,21 @@ bspl_status build_table(bspl_table* t, const float* d_coefs, bool padded_input,
     }
     const int64_t npts = (int64_t)in.px * in.py * in.pz;
     const unsigned grid = (unsigned)std::min<int64_t>(npts, 65536);
+    const int64_t bs = in.block_splines ? in.block_splines : np;
     switch (in.dtype) {
     case BSPL_F32:
         hipLaunchKernelGGL(pad_kernel<BSPL_F32>, dim3(grid), dim3(256), 0, s, d_coefs,
-                           padded_input ? 1 : 0, in.nx, in.ny, in.nz, nsp, np, t->d_scales,
+                           padded_input ? 1 : 0, in.nx, in.ny, in.nz, nsp, np, bs, t->d_scales,
                            t->d_table);
         break;
     case BSPL_F16:
         hipLaunchKernelGGL(pad_kernel<BSPL_F16>, dim3(grid), dim3(256), 0, s, d_coefs,
-                           padded_input ? 1 : 0, in.nx, in.ny, in.nz, nsp, np, t->d_scales,
+                           padded_input ? 1 : 0, in.nx, in.ny, in.nz, nsp, np, bs, t->d_scales,
                            t->d_table);
         break;
     default:
         hipLaunchKernelGGL(pad_kernel<BSPL_BF16>, dim3(grid), dim3(256), 0, s, d_coefs,
-                           padded_input ? 1 : 0, in.nx, in.ny, in.nz, nsp, np, t->d_scales,
+                           padded_input ? 1 : 0, in.nx, in.ny, in.nz, nsp, np, bs, t->d_scales,
                            t->d_table);
         break;
     }

@@ -113,6 +113,10 @@ bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, floa
     d.xstride = (uint32_t)((int64_t)in.py * in.pz * in.row_bytes);
     d.nsplines = (int32_t)in.n_splines;
     d.nchunks = (int32_t)((in.n_splines + 64 * vw - 1) / (64 * vw));
+    // a tile of 64*vw splines lies in one block (block_splines is a multiple)
+    d.block_bytes = in.block_splines ? in.block_bytes : 0;
+    d.chunks_per_block = in.block_splines ? (int32_t)(in.block_splines / (64 * vw))
+                                          : std::max(d.nchunks, 1);
     d.xgroups = (d.nchunks + wx - 1) / wx;
     const int vb = 4 * vw;
     d.vec_store = (ldo % vw == 0) && aligned(v, vb) && aligned(g, vb) && aligned(lh, vb) ? 1 : 0;
@@ -144,7 +148,7 @@ const char* spline_status_string(bspl_status s) {
 const char* spline_last_error(void) { return g_last_error; }
 
 bspl_status spline_layout_query(int nx, int ny, int nz, int64_t n_splines, bspl_dtype dtype,
-                                bspl_table_info* out) {
+                                unsigned flags, bspl_table_info* out) {
     if (!out) return fail(BSPL_EINVAL, "out is NULL");
     if (nx <= 0 || ny <= 0 || nz <= 0 || n_splines <= 0)
         return fail(BSPL_EINVAL, "grid (%d,%d,%d) and n_splines %lld must be positive", nx, ny,
@@ -160,12 +164,21 @@ bspl_status spline_layout_query(int nx, int ny, int nz, int64_t n_splines, bspl_
     i.dtype = dtype;
     i.elem_bytes = dtype == BSPL_F32 ? 4 : 2;
     const int64_t per_row = 128 / i.elem_bytes;
-    i.n_padded = (n_splines + per_row - 1) / per_row * per_row;
-    i.row_bytes = i.n_padded * i.elem_bytes;
+    const int64_t bs = block_splines_of(dtype);
+    if ((flags & BSPL_LAYOUT_BLOCKED) && n_splines > bs) {
+        // [n_padded / bs][px][py][pz][bs]
+        i.n_padded = (n_splines + bs - 1) / bs * bs;
+        i.block_splines = bs;
+        i.row_bytes = bs * i.elem_bytes;
+        i.block_bytes = (int64_t)i.px * i.py * i.pz * i.row_bytes;
+    } else {
+        i.n_padded = (n_splines + per_row - 1) / per_row * per_row;
+        i.row_bytes = i.n_padded * i.elem_bytes;
+    }
     // overflow-checked px*py*pz*row_bytes
-    const double est = (double)i.px * i.py * i.pz * (double)i.row_bytes;
+    const double est = (double)i.px * i.py * i.pz * (double)i.n_padded * i.elem_bytes;
     if (est > 9.0e18) return fail(BSPL_EUNSUPPORTED, "table of %.3g bytes overflows", est);
-    i.table_bytes = (int64_t)i.px * i.py * i.pz * i.row_bytes;
+    i.table_bytes = (int64_t)i.px * i.py * i.pz * i.n_padded * i.elem_bytes;
     // the 4x4x4 block of a cell must span < 4 GiB (32-bit offsets in kernels)
     const double span = 3.0 * ((double)i.py * i.pz * i.row_bytes + (double)i.pz * i.row_bytes +
                                (double)i.row_bytes) + (double)i.row_bytes;
@@ -226,13 +239,14 @@ bspl_status create_table(bspl_table** out, int nx, int ny, int nz, int64_t n_spl
     if (!out) return fail(BSPL_EINVAL, "out is NULL");
     *out = nullptr;
     if (!coefs) return fail(BSPL_EINVAL, "coefs is NULL");
-    if (flags & ~(BSPL_COEFS_PADDED | BSPL_COEFS_DEVICE | BSPL_COEFS_GRID_VALUES))
+    if (flags & ~(BSPL_COEFS_PADDED | BSPL_COEFS_DEVICE | BSPL_COEFS_GRID_VALUES |
+                  BSPL_LAYOUT_BLOCKED))
         return fail(BSPL_EINVAL, "unknown flags 0x%x", flags);
     if ((flags & BSPL_COEFS_PADDED) && (flags & BSPL_COEFS_GRID_VALUES))
         return fail(BSPL_EINVAL, "grid values are unpadded: BSPL_COEFS_PADDED with "
                                  "BSPL_COEFS_GRID_VALUES");
     bspl_table_info info{};
-    bspl_status st = spline_layout_query(nx, ny, nz, n_splines, dtype, &info);
+    bspl_status st = spline_layout_query(nx, ny, nz, n_splines, dtype, flags, &info);
     if (st != BSPL_OK) return st;
     const int ncell[3] = {nx, ny, nz};
     double gm[3][3];
@@ -369,10 +383,10 @@ bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos
                                bspl_tile* out) {
     if (!t || !out) return fail(BSPL_EINVAL, "table or out is NULL");
     if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
-    char key[256];
+    char key[256], prefix[64];
     const int32_t nc[3] = {t->info.nx, t->info.ny, t->info.nz};
-    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos,
-               t->lattice ? "single-lattice" : "single");
+    key_prefix(prefix, sizeof prefix, "single", t);
+    wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos, prefix);
     bspl_tile tile;
     if (wisdom_lookup(key, &tile) && tile_valid(tile, t->info.dtype)) {
         *out = tile;

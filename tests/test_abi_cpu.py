@@ -54,6 +54,48 @@ def test_layout_query(shape, dtype, np_, nbytes):
     assert info["data"] is None and info["scales"] is None
 
 
+@pytest.mark.parametrize("shape,dtype,bs,np_", [
+    ((48, 48, 48, 2048), "f32", 256, 2048),
+    ((48, 48, 48, 1152), "f32", 256, 1280),   # ragged last block: 4.5 -> 5 blocks
+    ((48, 48, 48, 2048), "f16", 512, 2048),
+    ((7, 8, 9, 600), "bf16", 512, 1024),
+    ((96, 96, 96, 4096), "f16", 512, 4096),
+])
+def test_layout_query_blocked(shape, dtype, bs, np_):
+    """Spline-blocked tables: [n_padded/B][px][py][pz][B], a 1 KB z row,
+    blocks of px*py*pz rows; the same bytes as the plain table when N needs
+    no extra padding."""
+    info = B.spline_layout_query(*shape, dtype, B.BSPL_LAYOUT_BLOCKED)
+    eb = 4 if dtype == "f32" else 2
+    pts = (shape[0] + 3) * (shape[1] + 3) * (shape[2] + 3)
+    assert info["block_splines"] == bs and info["n_padded"] == np_
+    assert info["row_bytes"] == bs * eb == 1024
+    assert info["block_bytes"] == pts * 1024
+    assert info["table_bytes"] == (np_ // bs) * info["block_bytes"] == pts * np_ * eb
+    plain = B.spline_layout_query(*shape, dtype)
+    assert plain["block_splines"] == 0 and plain["block_bytes"] == 0
+    if np_ == plain["n_padded"]:
+        assert info["table_bytes"] == plain["table_bytes"]
+
+
+def test_layout_query_blocked_single_block_is_plain():
+    for dtype, n in (("f32", 256), ("f32", 200), ("f16", 512), ("bf16", 64)):
+        info = B.spline_layout_query(7, 8, 9, n, dtype, B.BSPL_LAYOUT_BLOCKED)
+        assert info == B.spline_layout_query(7, 8, 9, n, dtype)
+
+
+def test_layout_select_validates_and_skips_single_block_shapes():
+    out = ctypes.c_uint(99)
+    f = B.lib.spline_layout_select
+    assert f(8, 8, 8, 2048, 0, 2, 64, None, None, None) == B.BSPL_EINVAL  # NULL layout
+    assert f(8, 8, 8, 2048, 0, 5, 64, None, ctypes.byref(out), None) == B.BSPL_EINVAL
+    assert f(8, 8, 8, 2048, 0, 2, 0, None, ctypes.byref(out), None) == B.BSPL_EINVAL
+    assert f(8, 8, 8, 2048, 9, 2, 64, None, ctypes.byref(out), None) == B.BSPL_EINVAL
+    # at most one block: the layouts coincide, decided without the device
+    assert B.spline_layout_select(8, 8, 8, 256, "f32", "vgh", 64) == 0
+    assert B.spline_layout_select(8, 8, 8, 512, "f16", "vgh", 64) == 0
+
+
 def test_layout_query_rejects():
     with pytest.raises(B.BsplineError) as e:
         B.spline_layout_query(0, 4, 4, 8)
@@ -132,6 +174,17 @@ def test_fit_validates_before_touching_the_device():
     assert "GRID_VALUES" in B.spline_last_error()
 
 
+def test_table_info_struct_matches_header():
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {\n    int32_t nx, ny, nz;"):]
+    body = body[:body.index("} bspl_table_info;")]
+    fields = []
+    for m in re.finditer(r"^\s+(?:const )?\w+\*? ?\*?\s*([\w, \[\]0-9]+);", body, re.M):
+        for name in m.group(1).split(","):
+            fields.append(re.sub(r"\[\d+\]", "", name).strip())
+    assert fields == [f for f, _ in B.bspl_table_info._fields_]
+
+
 def test_tile_struct_matches_header():
     text = open(HEADER).read()
     body = text[text.index("typedef struct {\n    int32_t vw;"):]
@@ -184,7 +237,8 @@ def test_wisdom_files(tmp_path):
     out = str(tmp_path / "out.txt")
     B.spline_wisdom_save(out)
     text = open(out).read()
-    assert "single|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 1 1\n" in text
+    # a line's time survives a load and save; a line without one stays without
+    assert "single|gfx950|f32|vgh|N64|16x16x16|p1024 2 2 1 0 1 1 12.500\n" in text
     assert "single|gfx950|f32|vgh|N64|16x16x16|p1 1 2 1 0 0 4\n" in text
     assert "|v|" not in text  # a line with too few fields is skipped
     with pytest.raises(B.BsplineError) as e:
