@@ -120,6 +120,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--profile", action="store_true", help="headline kernel only")
+    ap.add_argument("--blocked", action="store_true",
+                    help="profiling: a spline-blocked table instead of the plain one")
     ap.add_argument("--copy-probe", action="store_true", help="only a 1 GiB device copy")
     ap.add_argument("--tile", default=None,
                     help="profiling: fixed tile vw,wx,wy,grid,order instead of the wisdom")
@@ -137,6 +139,8 @@ def main(argv=None):
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args(argv)
+    if args.blocked and not args.profile:
+        ap.error("--blocked is for --profile runs")
 
     if (args.npos != NPOS or args.dtype != "f32" or args.batched) and not args.profile:
         ap.error("--npos, --dtype and --batched are for --profile runs only")
@@ -166,7 +170,8 @@ def main(argv=None):
     t0 = time.time()
     coef = synth.coef_table(*GRID, NSPL, stream=synth.table_stream(0))
     log(f"[bench] coefficients generated in {time.time() - t0:.1f}s")
-    t32 = B.spline_table_create(*GRID, NSPL, coef, args.dtype)
+    t32 = B.spline_table_create(*GRID, NSPL, coef, args.dtype,
+                                flags=B.BSPL_LAYOUT_BLOCKED if args.blocked else 0)
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
     npos = args.npos
@@ -280,6 +285,8 @@ def main(argv=None):
                 "hbm_gbs": A.batch_bytes(kind, "f32", NPOS, NSPL) / (ms_h * 1e-3) / 1e9,
                 "tile": list(ht.as_tuple())}
         B.spline_table_destroy(thex)
+        extra["layout"] = layout_extra(torch, B, synth, coef, t32, steps, warmup)
+        log("[bench] layout extra done")
         # interpolating coefficients from grid values (table set-up, once per
         # orbital set): one HBM read and one write per element and axis
         vals = torch.from_numpy(coef).to(dev)
@@ -503,6 +510,43 @@ def batched_extra(torch, B, A, synth, steps, warmup):
         for t in tabs:
             B.spline_table_destroy(t)
     res["f16_speedup_vs_f32"] = res["f16"]["evals_per_s"] / res["f32"]["evals_per_s"]
+    return res
+
+
+def layout_extra(torch, B, synth, coef, t32, steps, warmup):
+    """Plain against spline-blocked tables (the paper's AoSoA sub-tables), each
+    at its own autotuned tile: FP32 VGH on the headline's 512-position
+    batches and FP16 VGH on 4096 positions, with the layout that
+    spline_layout_select picks from those timings."""
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    res = {"workload": "eval_vgh on the 48^3 x N=2048 coefficients; blocks of 256 (FP32) or "
+                       "512 (FP16) splines, [N/B][51][51][51][B]; uniform positions, "
+                       "batches cycled"}
+    for dt, npos, nb in (("f32", NPOS, NBATCH), ("f16", 4096, 4)):
+        batches = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0),
+                                                    batch=b)).to(dev) for b in range(nb)]
+        v = torch.empty(npos, NSPL, device=dev)
+        g = torch.empty(npos, 3, NSPL, device=dev)
+        h = torch.empty(npos, 6, NSPL, device=dev)
+        row = {}
+        for name, flags in (("plain", 0), ("blocked", B.BSPL_LAYOUT_BLOCKED)):
+            t = t32 if (dt == "f32" and flags == 0) else B.spline_table_create(
+                *GRID, NSPL, coef, dt, flags=flags)
+            tile = B.spline_autotune(t, "vgh", npos)
+            ms = timed(torch, lambda i: B.spline_eval(t, "vgh", npos, batches[i % nb], v, g, h,
+                                                      NSPL, tile=tile, stream=stream),
+                       max(100, steps // 4), warmup)
+            row[f"{name}_us_per_launch"] = ms * 1e3
+            row[f"{name}_evals_per_s"] = npos * NSPL / (ms * 1e-3)
+            row[f"{name}_tile"] = list(tile.as_tuple())
+            if t != t32:
+                B.spline_table_destroy(t)
+        row["blocked_over_plain_time"] = row["blocked_us_per_launch"] / row["plain_us_per_launch"]
+        sel = B.spline_layout_select(*GRID, NSPL, dt, "vgh", npos)
+        row["selected"] = "blocked" if sel == B.BSPL_LAYOUT_BLOCKED else "plain"
+        res[f"{dt}_vgh_{npos}pos"] = row
+        del v, g, h, batches
     return res
 
 
