@@ -54,14 +54,17 @@ def test_random_configuration(case):
     frac = rng.uniform(-2.0, 3.0, (3, npos))
     pos = np.ascontiguousarray(cell.T @ frac)
     ldo = n + int(rng.integers(0, 5))
-    h = B.spline_table_create_lattice(*dims, n, coef, cell, dtype)
+    # the table layout comes from a generator of its own, so the cases above
+    # stay what they were; both layouts must give the oracle's values
+    flags = B.BSPL_LAYOUT_BLOCKED if np.random.default_rng(7000 + case).random() < 0.5 else 0
+    h = B.spline_table_create_lattice(*dims, n, coef, cell, dtype, flags)
     try:
         gpu, raw = run_gpu(B, h, kind, pos, n, ldo=ldo, tile=tile)
     finally:
         B.spline_table_destroy(h)
     assert_canary(raw, n)
     ref = oracle.evaluate_lattice(kind, dequantized(coef, dtype), pos, cell)
-    label = f"case {case}: {dims} N={n} {dtype} {kind} tile {tile} npos {npos}"
+    label = f"case {case}: {dims} N={n} {dtype} {kind} tile {tile} npos {npos} flags {flags}"
     # a component whose values all vanish (n_d = 1 makes its derivatives 0)
     # is normalised by the natural scale max|V| * (1/Delta)^order
     inv_delta = float(np.max(np.abs(np.linalg.inv(cell)) * np.array(dims)[None, :]))
@@ -89,6 +92,7 @@ def test_random_plan(case):
     wy = int(rng.choice([w for w in (1, 2) if w * wx <= 8]))
     tile = (vw, wx, wy, int(rng.choice([0, 64, 256])), int(rng.integers(0, 3)), 1)
     dev = torch.device("cuda")
+    lay = np.random.default_rng(8000 + case)  # table layouts, apart from the cases' draws
     tabs, coefs, cells, poss, outs, npos, ldos = [], [], [], [], [], [], []
     try:
         for _ in range(nt):
@@ -97,7 +101,8 @@ def test_random_plan(case):
             m = int(rng.integers(0, 120)) if rng.random() > 0.15 else 0
             cell = _random_cell(rng)
             coef = rng.uniform(-1, 1, dims + (n,)).astype(np.float32)
-            tabs.append(B.spline_table_create_lattice(*dims, n, coef, cell, dtype))
+            flags = B.BSPL_LAYOUT_BLOCKED if lay.random() < 0.5 else 0
+            tabs.append(B.spline_table_create_lattice(*dims, n, coef, cell, dtype, flags))
             coefs.append(coef)
             cells.append(cell)
             pos = np.ascontiguousarray(cell.T @ rng.uniform(-1.0, 2.0, (3, max(m, 1))))[:, :m]
@@ -155,6 +160,7 @@ def test_random_ratio(case):
     coef = rng.uniform(-1, 1, dims + (n,)).astype(np.float32)
     pos = np.ascontiguousarray(cell.T @ rng.uniform(-1.0, 2.0, (3, npos)))
     ld = n + int(rng.integers(0, 4))
+    flags = B.BSPL_LAYOUT_BLOCKED if np.random.default_rng(9500 + case).random() < 0.5 else 0
     ainv = rng.standard_normal((npos, ld)).astype(np.float32)
     full = oracle.evaluate_lattice(kind, dequantized(coef, dtype).astype(np.float64), pos, cell)
     comps = [full["v"]]
@@ -168,7 +174,7 @@ def test_random_ratio(case):
     ref = np.stack([(x * a).sum(axis=1) for x in comps], axis=1)
     scale = np.array([np.abs(x * a).sum(axis=1).max() for x in comps]) + 1e-300
     dev = torch.device("cuda")
-    h = B.spline_table_create_lattice(*dims, n, coef, cell, dtype)
+    h = B.spline_table_create_lattice(*dims, n, coef, cell, dtype, flags)
     try:
         out = torch.full((npos, ref.shape[1]), 7.0, dtype=torch.float64, device=dev)
         B.spline_eval_ratio(h, kind, npos, torch.from_numpy(pos).to(dev),
