@@ -22,8 +22,10 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import platform
+import subprocess
 import sys
 import time
 
@@ -255,9 +257,21 @@ def main(argv=None):
         },
     }
 
+    # context: the fraction of a batch's row reads that are unique (no
+    # reuse credited in the algorithmic bytes), lambda = 64 npos / points
+    lam = 64.0 * NPOS / float((GRID[0] + 3) * (GRID[1] + 3) * (GRID[2] + 3))
+    line["config"]["unique_row_fraction"] = (1.0 - math.exp(-lam)) / lam
+    line["gpu_clocks"] = gpu_clocks()
     extra = {}
     if not args.no_extras:
-        # VGL on the same table and batches
+        # V and VGL on the same table and batches
+        tile_v = B.spline_autotune(t32, "v", NPOS)
+        ms_v = timed(torch, lambda i: B.spline_eval(t32, "v", NPOS, pp[i % nbatch], v, None, None,
+                                                    ldo, tile=tile_v, stream=stream),
+                     max(100, steps // 2), warmup)
+        extra["v"] = {"evals_per_s": evals / (ms_v * 1e-3), "us_per_launch": ms_v * 1e3,
+                      "hbm_gbs": A.batch_bytes("v", "f32", NPOS, NSPL) / (ms_v * 1e-3) / 1e9,
+                      "tile": list(tile_v.as_tuple())}
         def vgl_step(i):
             B.spline_eval_vgl(t32, NPOS, pp[i % nbatch], vp, gp, lp, ldo, stream)
         tile_l = B.spline_autotune(t32, "vgl", NPOS)
@@ -287,6 +301,17 @@ def main(argv=None):
         B.spline_table_destroy(thex)
         extra["layout"] = layout_extra(torch, B, synth, coef, t32, steps, warmup)
         log("[bench] layout extra done")
+        # the FP16 table on the headline's own 512-position batches
+        t16 = B.spline_table_create(*GRID, NSPL, coef, "f16")
+        tile16 = B.spline_autotune(t16, "vgh", NPOS)
+        ms16 = timed(torch, lambda i: B.spline_eval(t16, "vgh", NPOS, pp[i % nbatch], v, g, h,
+                                                    ldo, tile=tile16, stream=stream),
+                     max(100, steps // 2), warmup)
+        B.spline_table_destroy(t16)
+        extra["f16_headline_batches"] = {
+            "evals_per_s": evals / (ms16 * 1e-3), "us_per_launch": ms16 * 1e3,
+            "hbm_gbs": A.batch_bytes("vgh", "f16", NPOS, NSPL) / (ms16 * 1e-3) / 1e9,
+            "tile": list(tile16.as_tuple()), "speedup_vs_f32_headline": ms / ms16}
         # interpolating coefficients from grid values (table set-up, once per
         # orbital set): one HBM read and one write per element and axis
         vals = torch.from_numpy(coef).to(dev)
@@ -511,6 +536,21 @@ def batched_extra(torch, B, A, synth, steps, warmup):
             B.spline_table_destroy(t)
     res["f16_speedup_vs_f32"] = res["f16"]["evals_per_s"] / res["f32"]["evals_per_s"]
     return res
+
+
+def gpu_clocks():
+    """Current and available shader/memory clocks from rocm-smi (a child
+    process), or None where it cannot report them."""
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=30)
+        data = json.loads(r.stdout)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        return None
+    card = data.get("card0") if isinstance(data, dict) else None
+    if not isinstance(card, dict):
+        return None
+    return {k: v for k, v in card.items() if "clock" in k.lower() or "clk" in k.lower()}
 
 
 def layout_extra(torch, B, synth, coef, t32, steps, warmup):
