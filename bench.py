@@ -526,15 +526,22 @@ def batched_extra(torch, B, A, synth, steps, warmup):
                  for b in range(nb)]
         ms = timed(torch, lambda i: B.spline_batch_execute(plans[i % nb], stream),
                    max(50, steps // 10), warmup)
+        # the same plans issued as plain kernel launches (no graph)
+        ms_d = timed(torch, lambda i: B.spline_batch_launch(plans[i % nb], stream),
+                     max(50, steps // 10), warmup)
         alg = sum(A.batch_bytes("vgh", dt, m, n) for (_, n, m) in CFG4)
         res[dt] = {"evals_per_s": evals / (ms * 1e-3), "us_per_replay": ms * 1e3,
                    "hbm_gbs": alg / (ms * 1e-3) / 1e9,
+                   "direct_launch_evals_per_s": evals / (ms_d * 1e-3),
+                   "us_per_direct_launch": ms_d * 1e3,
                    "tile": list(B.spline_batch_plan_tile(plans[0]).as_tuple())}
         for pl in plans:
             B.spline_batch_plan_destroy(pl)
         for t in tabs:
             B.spline_table_destroy(t)
     res["f16_speedup_vs_f32"] = res["f16"]["evals_per_s"] / res["f32"]["evals_per_s"]
+    res["f16_speedup_vs_f32_direct_launch"] = (res["f16"]["direct_launch_evals_per_s"] /
+                                               res["f32"]["direct_launch_evals_per_s"])
     return res
 
 

@@ -99,6 +99,7 @@ _SIGS = {
                                         _P(_vp), _P(_vp), _P(_vp), _P(_i64), _P(bspl_tile),
                                         ctypes.c_char_p, _vp]),
     "spline_batch_execute": (_int, [_vp, _vp]),
+    "spline_batch_launch": (_int, [_vp, _vp]),
     "spline_batch_rebind": (_int, [_vp, _int, _vp, _vp, _vp, _vp]),
     "spline_batch_plan_tile": (_int, [_vp, _P(bspl_tile)]),
     "spline_batch_plan_destroy": (_int, [_vp]),
@@ -292,6 +293,10 @@ def spline_batch_plan_create(tables, npos, kind, pos, v, g=None, lh=None, ldo=No
 
 def spline_batch_execute(plan, stream=None) -> None:
     _check(lib.spline_batch_execute(plan, _stream(stream)), "spline_batch_execute")
+
+
+def spline_batch_launch(plan, stream=None) -> None:
+    _check(lib.spline_batch_launch(plan, _stream(stream)), "spline_batch_launch")
 
 
 def spline_batch_rebind(plan, i, pos, v, g=None, lh=None) -> None:

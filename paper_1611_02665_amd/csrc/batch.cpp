@@ -363,6 +363,23 @@ bspl_status spline_batch_execute(bspl_plan* p, void* stream) {
     return BSPL_OK;
 }
 
+bspl_status spline_batch_launch(bspl_plan* p, void* stream) {
+    if (!p) return fail(BSPL_EINVAL, "plan is NULL");
+    if (p->args.total_groups == 0) return BSPL_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (p->tile.order > 0) {
+        hipKernelNodeParams op;
+        if (order_params(p, &op))
+            BSPL_HIP(hipLaunchKernel(op.func, op.gridDim, op.blockDim, op.kernelParams,
+                                     op.sharedMemBytes, s));
+    }
+    const void* fn = multi_kernel_ptr(p->dtype, p->kind, p->tile.vw, plan_lattice(*p));
+    void* params[] = {&p->args};
+    BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)grid_for(p->args, p->tile)),
+                             dim3(64 * p->tile.wx * p->tile.wy), params, 0, s));
+    return BSPL_OK;
+}
+
 bspl_status spline_batch_rebind(bspl_plan* p, int i, const double* pos, float* v, float* g,
                                 float* lh) {
     if (!p) return fail(BSPL_EINVAL, "plan is NULL");

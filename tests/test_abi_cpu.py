@@ -207,6 +207,7 @@ def test_null_handles():
     assert B.lib.spline_tile_select(None, 0, 1, ctypes.byref(t)) == B.BSPL_EINVAL
     assert B.lib.spline_autotune(None, 0, 1, None, None, None) == B.BSPL_EINVAL
     assert B.lib.spline_batch_execute(None, None) == B.BSPL_EINVAL
+    assert B.lib.spline_batch_launch(None, None) == B.BSPL_EINVAL
     assert B.lib.spline_batch_rebind(None, 0, None, None, None, None) == B.BSPL_EINVAL
     assert B.lib.spline_batch_plan_tile(None, ctypes.byref(t)) == B.BSPL_EINVAL
 

@@ -205,3 +205,79 @@ def test_config4_batched_sampled():
     finally:
         for h in handles:
             B.spline_table_destroy(h)
+
+
+@pytest.mark.parametrize("tile", [(1, 2, 1, 0, 0, 1), (2, 4, 1, 0, 1, 1), (4, 1, 2, 64, 2, 1)])
+def test_batch_launch_matches_execute(tile):
+    """spline_batch_launch issues the plan's kernels without the graph: the
+    same bits as a graph replay, before and after a rebind, and inside a
+    stream capture replayed several times with eager work in between."""
+    shapes = [(6, 7, 5, 300), (5, 5, 6, 130), (7, 6, 6, 520)]
+    npos = [77, 40, 150]
+    coefs = [synth.coef_table(*s, stream=400 + i) for i, s in enumerate(shapes)]
+    hs = [B.spline_table_create(*s, c, "f32") for s, c in zip(shapes, coefs)]
+    dev = torch.device("cuda")
+
+    def sets(stream0):
+        pos = [torch.from_numpy(synth.positions(m, stream=stream0 + i) * 2 - 0.5).to(dev)
+               for i, m in enumerate(npos)]
+        outs = [_outs("vgh", m, s[3]) for m, s in zip(npos, shapes)]
+        return pos, outs
+
+    def host(outs):
+        return [{k: t.cpu().numpy() for k, t in o.items()} for o in outs]
+
+    try:
+        pos, outs = sets(410)
+        plan = B.spline_batch_plan_create(hs, npos, "vgh", pos, [o["v"] for o in outs],
+                                          [o["g"] for o in outs], [o["h"] for o in outs],
+                                          [s[3] for s in shapes], tile=tile)
+        try:
+            B.spline_batch_execute(plan)
+            torch.cuda.synchronize()
+            ref = host(outs)
+            for o in outs:
+                for t in o.values():
+                    t.fill_(7.0)
+            B.spline_batch_launch(plan)
+            torch.cuda.synchronize()
+            got = host(outs)
+            for a, b in zip(ref, got):
+                for k in a:
+                    assert np.array_equal(a[k], b[k]), k
+            # rebind table 1 to new buffers: launch sees it at once
+            pos2, outs2 = sets(420)
+            B.spline_batch_rebind(plan, 1, pos2[1], outs2[1]["v"], outs2[1]["g"], outs2[1]["h"])
+            B.spline_batch_launch(plan)
+            torch.cuda.synchronize()
+            got2 = host(outs2)[1]
+            ref2 = oracle.evaluate("vgh", coefs[1], pos2[1].cpu().numpy())
+            assert_close("vgh", {k: a[..., :shapes[1][3]].astype(np.float64)
+                                 for k, a in got2.items()}, ref2, label="launch after rebind")
+            # captured into a caller's graph; each replay checked against the eager result
+            B.spline_batch_rebind(plan, 1, pos[1], outs[1]["v"], outs[1]["g"], outs[1]["h"])
+            gs = torch.cuda.Stream()
+            gs.wait_stream(torch.cuda.current_stream())
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(gs):
+                B.spline_batch_launch(plan, gs.cuda_stream)
+                torch.cuda.synchronize()
+                with torch.cuda.graph(graph, stream=gs):
+                    B.spline_batch_launch(plan, gs.cuda_stream)
+            torch.cuda.synchronize()
+            for _ in range(3):
+                for o in outs:
+                    for t in o.values():
+                        t.fill_(3.0)
+                torch.cuda.synchronize()
+                graph.replay()
+                torch.cuda.synchronize()
+                for a, b in zip(ref, host(outs)):
+                    for k in a:
+                        assert np.array_equal(a[k], b[k]), ("replay", k)
+            del graph
+        finally:
+            B.spline_batch_plan_destroy(plan)
+    finally:
+        for h in hs:
+            B.spline_table_destroy(h)
