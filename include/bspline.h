@@ -52,23 +52,41 @@
 extern "C" {
 #endif
 
+/* Each enum also has a _ENUM_MIN and _ENUM_MAX member.  They are not values
+ * to pass: they make every 32-bit int a valid value of the type, so that a
+ * C caller's out-of-range value reaches the library well defined (and is
+ * rejected with BSPL_EINVAL) in C++ as well.                              */
 typedef enum {
     BSPL_OK = 0,
     BSPL_EINVAL = 1,       /* bad argument: NULL, non-positive size, bad enum */
     BSPL_ENOMEM = 2,       /* device or host allocation failed */
     BSPL_EDEVICE = 3,      /* a HIP call failed; see spline_last_error() */
     BSPL_EUNSUPPORTED = 4, /* valid request this build does not support */
-    BSPL_EIO = 5           /* wisdom file could not be read or written */
+    BSPL_EIO = 5,          /* wisdom file could not be read or written */
+    BSPL_STATUS_ENUM_MIN = -2147483647 - 1,
+    BSPL_STATUS_ENUM_MAX = 2147483647
 } bspl_status;
 
 /* Storage type of the coefficient table.  F16 and BF16 tables hold c/s_n
  * rounded to nearest-even, with a per-spline FP32 scale s_n = 2^ceil(log2
  * max|c_n|) (1 for an all-zero spline); evaluation converts to FP32,
  * accumulates in FP32 and multiplies each output by s_n once.             */
-typedef enum { BSPL_F32 = 0, BSPL_F16 = 1, BSPL_BF16 = 2 } bspl_dtype;
+typedef enum {
+    BSPL_F32 = 0,
+    BSPL_F16 = 1,
+    BSPL_BF16 = 2,
+    BSPL_DTYPE_ENUM_MIN = -2147483647 - 1,
+    BSPL_DTYPE_ENUM_MAX = 2147483647
+} bspl_dtype;
 
 /* Which outputs to produce (paper Fig. 3: V, VGL, VGH). */
-typedef enum { BSPL_V = 0, BSPL_VGL = 1, BSPL_VGH = 2 } bspl_kind;
+typedef enum {
+    BSPL_V = 0,
+    BSPL_VGL = 1,
+    BSPL_VGH = 2,
+    BSPL_KIND_ENUM_MIN = -2147483647 - 1,
+    BSPL_KIND_ENUM_MAX = 2147483647
+} bspl_kind;
 
 /* spline_table_create flags */
 #define BSPL_COEFS_PADDED 0x1u /* coefs are [nx+3][ny+3][nz+3][N], used as-is */

@@ -141,6 +141,7 @@ const char* spline_status_string(bspl_status s) {
     case BSPL_EDEVICE: return "BSPL_EDEVICE: HIP runtime error";
     case BSPL_EUNSUPPORTED: return "BSPL_EUNSUPPORTED: unsupported request";
     case BSPL_EIO: return "BSPL_EIO: wisdom file error";
+    default: break;
     }
     return "unknown bspl_status";
 }
