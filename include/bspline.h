@@ -287,6 +287,12 @@ bspl_status spline_eval_ratio(const bspl_table* t, bspl_kind kind, int64_t npos,
  * and npos * N >= 4M, and the latency mode (split 4) for npos <= 16.      */
 bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos,
                                bspl_tile* out);
+/* For experiments the environment variable BSPL_TILE="vw,wx,wy,grid,order"
+ * or "vw,wx,wy,grid,order,split" overrides both the tuned and the default
+ * decomposition here, in every evaluation given tile = NULL and in batch
+ * plans created with tile = NULL (whose sweep it replaces; split must then
+ * be 0 or 1).  A value that does not parse or is not valid for the table's
+ * dtype makes those calls return EINVAL.  Ratios are not affected.        */
 
 /* Autotuner (the paper tunes the tile size N_b once per machine by an
  * exhaustive sweep and plans an FFTW-like "wisdom" file, section

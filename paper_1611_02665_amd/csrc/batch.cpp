@@ -316,8 +316,14 @@ bspl_status spline_batch_plan_create(bspl_plan** out, int ntables, const bspl_ta
         char key[2048];
         batch_key(*p, key, sizeof key);
         bspl_tile t;
-        if (wisdom_path) (void)spline_wisdom_load(wisdom_path);
-        if (wisdom_lookup(key, &t) && tile_valid(t, p->dtype) && t.split <= 1) {
+        bool bad = false;
+        const bool forced = env_tile(&t, &bad);
+        if (forced && (bad || !tile_valid(t, p->dtype) || t.split > 1)) {
+            spline_batch_plan_destroy(p);
+            return fail(BSPL_EINVAL, "BSPL_TILE is not a valid plan tile for dtype %d", p->dtype);
+        }
+        if (wisdom_path && !forced) (void)spline_wisdom_load(wisdom_path);
+        if (forced || (wisdom_lookup(key, &t) && tile_valid(t, p->dtype) && t.split <= 1)) {
             p->tile = t;
         } else {
             float us = 0;

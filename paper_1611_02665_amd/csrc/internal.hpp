@@ -86,6 +86,8 @@ bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, floa
                       TableDesc* out);
 
 bool tile_valid(const bspl_tile& tile, int dtype);
+// The BSPL_TILE environment override: false when unset; *bad when unparsable.
+bool env_tile(bspl_tile* out, bool* bad);
 bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos);
 
 // Kernel launchers (eval_launch.hip; kernels in eval_device.hpp).

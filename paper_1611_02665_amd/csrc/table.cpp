@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <cstdlib>
 
 #include "internal.hpp"
 
@@ -74,6 +75,26 @@ bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos) {
     if (64.0 * (double)npos >= 0.5 * points && (double)npos * (double)n >= 4194304.0)
         tile.order = 1;
     return tile;
+}
+
+// BSPL_TILE="vw,wx,wy,grid,order[,split]" overrides the tuned and default
+// decompositions.  Returns false when the variable is unset; sets *bad when
+// it is set but cannot be parsed.
+bool env_tile(bspl_tile* out, bool* bad) {
+    *bad = false;
+    const char* e = std::getenv("BSPL_TILE");
+    if (!e || !*e) return false;
+    bspl_tile t{};
+    t.split = 1;
+    int used = 0, more = 0;
+    if (sscanf(e, "%d,%d,%d,%d,%d%n", &t.vw, &t.wx, &t.wy, &t.grid, &t.order, &used) != 5) {
+        *bad = true;
+        return true;
+    }
+    if (e[used] == ',' && sscanf(e + used, ",%d%n", &t.split, &more) == 1) used += more;
+    *bad = e[used] != '\0';
+    *out = t;
+    return true;
 }
 
 static bool aligned(const void* p, int bytes) {
@@ -384,11 +405,19 @@ bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos
                                bspl_tile* out) {
     if (!t || !out) return fail(BSPL_EINVAL, "table or out is NULL");
     if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
+    bspl_tile tile;
+    bool bad = false;
+    if (env_tile(&tile, &bad)) {
+        if (bad || !tile_valid(tile, t->info.dtype))
+            return fail(BSPL_EINVAL, "BSPL_TILE=\"%s\" is not a valid tile for dtype %d",
+                        std::getenv("BSPL_TILE"), (int)t->info.dtype);
+        *out = tile;
+        return BSPL_OK;
+    }
     char key[256], prefix[64];
     const int32_t nc[3] = {t->info.nx, t->info.ny, t->info.nz};
     key_prefix(prefix, sizeof prefix, "single", t);
     wisdom_key(key, sizeof key, t->info.dtype, kind, t->info.n_splines, nc, npos, prefix);
-    bspl_tile tile;
     if (wisdom_lookup(key, &tile) && tile_valid(tile, t->info.dtype)) {
         *out = tile;
         return BSPL_OK;
@@ -418,7 +447,8 @@ bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const
                         "tile (vw=%d wx=%d wy=%d grid=%d order=%d split=%d) invalid for dtype %d",
                         tl.vw, tl.wx, tl.wy, tl.grid, tl.order, tl.split, t->info.dtype);
     } else {
-        spline_tile_select(t, kind, npos, &tl);
+        const bspl_status ts = spline_tile_select(t, kind, npos, &tl);
+        if (ts != BSPL_OK) return ts;
     }
     TableDesc d;
     bspl_status st = make_desc(t, npos, pos, v, kind == BSPL_V ? nullptr : g,

@@ -597,3 +597,41 @@ def test_ratio_argument_errors(cfg1):
         B.spline_eval_ratio(t.h, "v", 4, p, None, 64, out)
     assert e.value.status == B.BSPL_EINVAL
     B.spline_eval_ratio(t.h, "v", 0, None, None, 64, None)
+
+
+def test_tile_environment_override(monkeypatch):
+    """BSPL_TILE overrides the tuned and default tiles of evaluations and
+    plans given no tile; a malformed or invalid value is an EINVAL."""
+    coef = synth.coef_table(6, 7, 8, 300, stream=440)
+    pos = synth.positions(50, stream=441)
+    with Table(coef, "f32") as t:
+        ref = run_gpu(B, t.h, "vgh", pos, 300, tile=(2, 2, 1, 0, 1, 1))[1]
+        monkeypatch.setenv("BSPL_TILE", "2,2,1,0,1")
+        assert B.spline_tile_select(t.h, "vgh", 50).as_tuple() == (2, 2, 1, 0, 1, 1)
+        got = run_gpu(B, t.h, "vgh", pos, 300)[1]
+        for k in ref:
+            assert np.array_equal(ref[k], got[k]), k
+        monkeypatch.setenv("BSPL_TILE", "1,1,1,0,0,4")
+        assert B.spline_tile_select(t.h, "v", 50).as_tuple() == (1, 1, 1, 0, 0, 4)
+        dev = torch.device("cuda")
+        p = torch.from_numpy(pos).to(dev)
+        v = torch.empty(50, 300, device=dev)
+        with pytest.raises(B.BsplineError) as e:  # a split tile is not a plan tile
+            B.spline_batch_plan_create([t.h], [50], "v", [p], [v], ldo=[300])
+        assert e.value.status == B.BSPL_EINVAL
+        monkeypatch.setenv("BSPL_TILE", "4,1,2,64,2")
+        plan = B.spline_batch_plan_create([t.h], [50], "v", [p], [v], ldo=[300])
+        try:
+            assert B.spline_batch_plan_tile(plan).as_tuple()[:5] == (4, 1, 2, 64, 2)
+        finally:
+            B.spline_batch_plan_destroy(plan)
+        for bad in ("2,2,1", "2,2,1,0,1,1,7", "2,2,1,0,1x", "8,1,1,0,0", "abc"):
+            monkeypatch.setenv("BSPL_TILE", bad)
+            with pytest.raises(B.BsplineError) as e:
+                B.spline_tile_select(t.h, "vgh", 50)
+            assert e.value.status == B.BSPL_EINVAL, bad
+            with pytest.raises(B.BsplineError) as e:
+                run_gpu(B, t.h, "vgh", pos, 300)
+            assert e.value.status == B.BSPL_EINVAL, bad
+        monkeypatch.delenv("BSPL_TILE")
+        run_gpu(B, t.h, "vgh", pos, 300)
