@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "launch_check.hpp"
 
 namespace bspl {
 
@@ -193,6 +194,7 @@ bspl_status fill_random_positions(double* pos, int64_t npos, const double box[3]
                                   hipStream_t s) {
     if (npos <= 0) return BSPL_OK;
     const int64_t n = 3 * npos;
+    clear_last_error();
     hipLaunchKernelGGL(random_positions, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos,
                        npos, box[0], box[1], box[2], salt);
     BSPL_HIP(hipGetLastError());

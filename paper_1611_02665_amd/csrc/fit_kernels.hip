@@ -25,6 +25,7 @@
 // FP32, which makes the three passes work in place (src may equal dst, so
 // neither pointer is restrict).
 #include "internal.hpp"
+#include "launch_check.hpp"
 
 namespace bspl {
 namespace {
@@ -137,6 +138,7 @@ bspl_status launch_fit(int nx, int ny, int nz, int64_t nspl, const float* src, f
         const double gain = 1.0 / (1.0 - pn);
         const int start_terms = n < kStartTerms ? n : kStartTerms;
         const float* in = d == 0 ? src : dst;
+        clear_last_error();
         if (n <= kLdsMaxN) {
             const int64_t blocks = (lines + 63) / 64;
             hipLaunchKernelGGL(fit_axis_lds_kernel, dim3((unsigned)blocks), dim3(64),

@@ -6,6 +6,7 @@
 // left for the evaluation kernels (paper: the coefficient array P is padded
 // and aligned, section "Baseline and miniQMC").
 #include "internal.hpp"
+#include "launch_check.hpp"
 
 #include <cmath>
 
@@ -103,6 +104,9 @@ bspl_status build_table(bspl_table* t, const float* d_coefs, bool padded_input,
     if (in.dtype != BSPL_F32) {
         if (hipMalloc((void**)&mx, sizeof(uint32_t) * nsp) != hipSuccess)
             return fail(BSPL_ENOMEM, "scale scratch of %lld bytes", (long long)(4 * nsp));
+    }
+    clear_last_error();
+    if (in.dtype != BSPL_F32) {
         hipLaunchKernelGGL(fill_u32, dim3(64), dim3(256), 0, s, mx, nsp, 0u);
         const unsigned gx = (unsigned)((nsp + 255) / 256);
         const unsigned gy = (unsigned)std::min<int64_t>(nrows, 1024);

@@ -173,3 +173,26 @@ def test_ordering_degenerate_distributions(cell):
                      label=f"{cell} grid points, ordered")
     finally:
         B.spline_table_destroy(h)
+
+
+def test_table_larger_than_device_memory_is_enomem():
+    """A 449 GB table (603^3 x 512 FP32 rows) cannot be allocated on a 288 GB
+    device: creation returns ENOMEM before it reads any coefficient, and the
+    library keeps working afterwards."""
+    info = B.spline_layout_query(600, 600, 600, 512, "f32")
+    free, total = torch.cuda.mem_get_info()
+    assert info["table_bytes"] > total
+    dev = torch.device("cuda")
+    dummy = torch.zeros(16, device=dev)  # never read: the table allocation fails first
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_table_create(600, 600, 600, 512, dummy, "f32", flags=B.BSPL_COEFS_DEVICE)
+    assert e.value.status == B.BSPL_ENOMEM
+    assert "hipMalloc(table)" in B.spline_last_error()
+    coef = synth.coef_table(4, 5, 6, 70, stream=195)
+    h = B.spline_table_create(4, 5, 6, 70, coef, "f32")
+    try:
+        pos = synth.positions(20, stream=196)
+        gpu, _ = run_gpu(B, h, "vgh", pos, 70)
+        assert_close("vgh", gpu, oracle.evaluate("vgh", coef, pos))
+    finally:
+        B.spline_table_destroy(h)
