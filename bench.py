@@ -58,9 +58,9 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(per_launch_alg_bytes, tile):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source with the same tile (else None)."""
+def read_counters(tile):
+    """The committed counter summary's values, if it was taken on the current
+    kernel source with the same tile (else None)."""
     if not os.path.exists(PMC_FILE):
         return None
     vals = {}
@@ -73,9 +73,25 @@ def read_traffic(per_launch_alg_bytes, tile):
         return None
     if vals.get("tile") != ",".join(str(x) for x in tile.as_tuple()):
         return None
+    return vals
+
+
+def read_traffic(per_launch_alg_bytes, tile):
+    """HBM bytes per launch from the committed counter summary (or None)."""
+    vals = read_counters(tile)
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals["hbm_bytes_per_launch"]) if vals else None
     except (KeyError, ValueError):
+        return None
+
+
+def read_l2_hit_rate(tile):
+    """L2 hits / (hits + misses) of the headline launch from the same summary."""
+    vals = read_counters(tile)
+    try:
+        hits = float(vals["l2_hits_per_dispatch"])
+        return hits / (hits + float(vals["l2_misses_per_dispatch"]))
+    except (KeyError, ValueError, TypeError, ZeroDivisionError):
         return None
 
 
@@ -252,6 +268,7 @@ def main(argv=None):
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            "l2_hit_rate": read_l2_hit_rate(tile),
             "alg_bytes_per_launch": alg_bytes,
             "bytes_per_eval": A.bytes_per_eval("vgh", "f32"),
         },
