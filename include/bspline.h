@@ -335,7 +335,8 @@ bspl_status spline_wisdom_save(const char* path);
  * covers every unit, or grid > 0 persistent workgroups striding over
  * them), replayed from a captured HIP graph (paper: independent AoSoA tiles and walkers,
  * section "Optimizations and Parallelization", Fig. 6).  All tables must
- * share one dtype.  npos[i] positions go to table i.  Buffers are bound at
+ * share one dtype; they may differ in shape, N, cell and layout (plain or
+ * spline-blocked).  npos[i] positions go to table i.  Buffers are bound at
  * plan creation:
  *   pos[i]   device [3][npos[i]] FP64
  *   v[i]     device [npos[i]][ldo[i]]
@@ -366,7 +367,7 @@ bspl_status spline_batch_execute(bspl_plan* p, void* stream);
 bspl_status spline_batch_launch(bspl_plan* p, void* stream);
 
 /* Rebind the buffers of table i in an existing plan (same npos and ldo
- * rules); takes effect from the next execute.                             */
+ * rules); takes effect from the next execute or launch.                   */
 bspl_status spline_batch_rebind(bspl_plan* p, int i, const double* pos, float* v,
                                 float* g, float* lh);
 
