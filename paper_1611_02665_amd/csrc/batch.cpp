@@ -1,6 +1,7 @@
 // Batched multi-table evaluation: one launch over a flattened
 // work list of (table, position block, spline-tile block) units, built once
-// into a HIP graph and replayed.
+// into a HIP graph and replayed (spline_batch_execute), or issued as the
+// same kernel launches without the graph (spline_batch_launch).
 //
 // This is the GPU form of the paper's independent AoSoA tiles and walkers
 // (section "Optimizations and Parallelization", Fig. 6): every unit is
