@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import (FP32_TOL, assert_canary, assert_close, bf16_to_f32, dequantized,
+from helpers import (FP32_TOL, assert_canary, assert_close, dequantized,
                      normalized_errors, padded_layout, quantize_bf16, quantize_f16, run_gpu)
 
 pytestmark = pytest.mark.gpu
