@@ -635,3 +635,56 @@ def test_tile_environment_override(monkeypatch):
             assert e.value.status == B.BSPL_EINVAL, bad
         monkeypatch.delenv("BSPL_TILE")
         run_gpu(B, t.h, "vgh", pos, 300)
+
+
+def test_concurrent_host_threads_share_a_table():
+    """Four host threads evaluate one table at once, each on its own stream,
+    with default, cell-ordered and latency-mode tiles (the ordered calls take
+    stream-ordered scratch, the wisdom cache is shared): every result equals
+    the serial one bit for bit."""
+    import threading
+
+    coef = synth.coef_table(9, 8, 10, 700, stream=450)
+    with Table(coef, "f32") as t:
+        dev = torch.device("cuda")
+        tiles = [None, (1, 2, 1, 0, 1, 1), (2, 4, 1, 0, 2, 1), (1, 1, 1, 0, 0, 4)]
+        jobs = []
+        for k in range(4):
+            pos = torch.from_numpy(synth.positions(40 + 30 * k, stream=451 + k)).to(dev)
+            jobs.append((pos, tiles[k]))
+        ref = []
+        for pos, tile in jobs:
+            n = pos.shape[1]
+            out = [torch.empty(n, 700, device=dev), torch.empty(n, 3, 700, device=dev),
+                   torch.empty(n, 6, 700, device=dev)]
+            B.spline_eval(t.h, "vgh", n, pos, *out, 700, tile=tile)
+            torch.cuda.synchronize()
+            ref.append([o.cpu() for o in out])
+        results = [None] * 4
+        errors = []
+
+        def work(k):
+            try:
+                pos, tile = jobs[k]
+                n = pos.shape[1]
+                stream = torch.cuda.Stream()
+                out = [torch.empty(n, 700, device=dev), torch.empty(n, 3, 700, device=dev),
+                       torch.empty(n, 6, 700, device=dev)]
+                torch.cuda.synchronize()
+                for _ in range(20):
+                    B.spline_eval(t.h, "vgh", n, pos, *out, 700, tile=tile,
+                                  stream=stream.cuda_stream)
+                stream.synchronize()
+                results[k] = [o.cpu() for o in out]
+            except Exception as e:  # reported below with its thread
+                errors.append((k, repr(e)))
+
+        threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        assert not errors, errors
+        for k in range(4):
+            for a, b in zip(ref[k], results[k]):
+                assert torch.equal(a, b), k
