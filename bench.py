@@ -280,6 +280,7 @@ def main(argv=None):
     line["config"]["unique_row_fraction"] = (1.0 - math.exp(-lam)) / lam
     line["gpu_clocks"] = gpu_clocks()
     extra = {}
+    keep = {}
     if not args.no_extras:
         # V and VGL on the same table and batches
         tile_v = B.spline_autotune(t32, "v", NPOS)
@@ -366,7 +367,7 @@ def main(argv=None):
         line["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
         extra["precision"] = precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup)
         log("[bench] precision extra done")
-        extra["batched"] = batched_extra(torch, B, A, synth, steps, warmup)
+        extra["batched"] = batched_extra(torch, B, A, synth, steps, warmup, keep)
         log("[bench] batched extra done")
         extra["latency"] = latency_extra(torch, B, synth, t32)
         log("[bench] latency extra done")
@@ -377,6 +378,8 @@ def main(argv=None):
     B.spline_table_destroy(t32)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(np, synth, coef)
+        line["cpu_baseline"]["per_config"] = cpu_oracle_configs(np, synth, coef,
+                                                               keep.get("cfg4_coefs"))
     print(json.dumps(line), flush=True)
     return 0
 
@@ -517,13 +520,16 @@ def batched_profile(torch, B, A, synth, args):
     return 0
 
 
-def batched_extra(torch, B, A, synth, steps, warmup):
+def batched_extra(torch, B, A, synth, steps, warmup, keep=None):
     """Four tables of uneven shape and batch size in one launch
-    replayed from a HIP graph, FP32 and FP16 tables."""
+    replayed from a HIP graph, FP32 and FP16 tables.  The host coefficients
+    are left in keep["cfg4_coefs"] for the CPU leg."""
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
     coefs = [synth.coef_table(*grid, n, stream=synth.table_stream(i))
              for i, (grid, n, _) in enumerate(CFG4)]
+    if keep is not None:
+        keep["cfg4_coefs"] = coefs
     npos = [c[2] for c in CFG4]
     nb = 2
     pos = [[torch.from_numpy(synth.positions(m, stream=synth.position_stream(i), batch=b))
@@ -784,6 +790,37 @@ def cpu_baseline(np, synth, coef, budget_cpu_s=12.0, max_batches=64):
             "sample": f"eval_vgh FP64 oracle (C, OpenMP over positions), {b} batches x "
                       f"{NPOS} positions x N={NSPL} of the same 48^3 table, {wall:.2f} s wall",
             "cpu_model": cpu, "nproc": os.cpu_count(), "single_core_value": one}
+
+
+def cpu_oracle_configs(np, synth, coef48, cfg4_coefs):
+    """The oracle's VGH rate on the other workloads, for scale: the 16^3 x 64
+    parity table and the 4096-position batch in full, 256 positions of each
+    four-table table (when the batched extra ran), and 256 positions of the
+    96^3 x 4096 table on 64 of its splines (the whole table is 16 GB)."""
+    import oracle
+
+    def rate(tab, pos):
+        t = time.perf_counter()
+        oracle.evaluate("vgh", tab, pos)
+        return pos.shape[1] * tab.shape[-1], time.perf_counter() - t
+
+    out = {"unit": "orbital-evals/s", "cores": oracle.num_threads()}
+    c1 = synth.coef_table(16, 16, 16, 64, stream=synth.table_stream(0))
+    e, w = rate(c1, synth.positions(1024, stream=synth.position_stream(0)))
+    out["16^3xN64, 1024 positions (full)"] = e / w
+    e, w = rate(coef48, synth.positions(4096, stream=synth.position_stream(0), batch=100))
+    out["48^3xN2048, 4096 positions (full; the FP16/BF16 batch, same oracle cost)"] = e / w
+    if cfg4_coefs is not None:
+        ev, wall = 0, 0.0
+        for i, c in enumerate(cfg4_coefs):
+            e, w = rate(c, synth.positions(256, stream=synth.position_stream(i)))
+            ev, wall = ev + e, wall + w
+        out["four tables, 256 positions each"] = ev / wall
+    cols = np.arange(0, 4096, 64)
+    c5 = synth.coef_table(96, 96, 96, 4096, stream=synth.table_stream(0), splines=cols)
+    e, w = rate(c5, synth.positions(256, stream=synth.position_stream(0)))
+    out["96^3xN4096, 256 positions on 64 of the splines"] = e / w
+    return out
 
 
 if __name__ == "__main__":
