@@ -200,3 +200,30 @@ def test_blocked_table_beyond_4_gib():
     finally:
         for h in hs:
             B.spline_table_destroy(h)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+@pytest.mark.parametrize("kind", ["v", "vgl", "vgh"])
+def test_blocked_ratio_reduced_precision(dtype, kind):
+    """Fused ratios on FP16/BF16 blocked tables (two blocks, ragged) equal
+    those on plain tables bit for bit, for every kind and two tiles."""
+    n = 900
+    coef = synth.coef_table(5, 6, 7, n, stream=340)
+    plain, blocked = _pair(coef, dtype)
+    dev = torch.device("cuda")
+    try:
+        pos = torch.from_numpy(synth.positions(90, stream=341) * 2 - 0.5).to(dev)
+        ainv = torch.from_numpy(np.random.default_rng(342).standard_normal((90, n))
+                                .astype(np.float32)).to(dev)
+        nc = {"v": 1, "vgl": 5, "vgh": 10}[kind]
+        for tile in ((2, 4, 1, 0, 0), (8, 1, 1, 0, 0)):
+            outs = []
+            for h in (plain, blocked):
+                o = torch.full((90, nc), 3.0, dtype=torch.float64, device=dev)
+                B.spline_eval_ratio(h, kind, 90, pos, ainv, n, o, tile=tile)
+                torch.cuda.synchronize()
+                outs.append(o.cpu().numpy())
+            assert np.array_equal(outs[0], outs[1]), (dtype, kind, tile)
+    finally:
+        B.spline_table_destroy(plain)
+        B.spline_table_destroy(blocked)
