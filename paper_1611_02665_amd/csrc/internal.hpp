@@ -168,7 +168,7 @@ int device_cu_count();
 // Autotuner pieces shared with the batched planner (autotune.cpp).
 // Candidate tiles of the sweep; split (latency-mode) tiles only for single
 // evaluations of at most kSplitMaxPositions positions.
-constexpr int64_t kSplitMaxPositions = 64;
+constexpr int64_t kSplitMaxPositions = 1024;
 std::vector<bspl_tile> tile_candidates(int dtype, int kind, int64_t max_nsplines, int64_t npos,
                                        bool persistent);
 bspl_status fill_random_positions(double* pos, int64_t npos, const double box[3], uint64_t salt,
