@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "internal.hpp"
@@ -201,23 +202,36 @@ bspl_status fill_random_positions(double* pos, int64_t npos, const double box[3]
     return BSPL_OK;
 }
 
-// Sweep tiles for a launch described by `run(tile, iteration)`.
+// Sweep tiles for a launch described by `run(tile, iteration)`: every
+// candidate timed briefly (median of 5), then the fastest few again with
+// more runs (median of 25), so that noise does not decide between tiles
+// a few percent apart.
 bspl_status sweep(const std::vector<bspl_tile>& cands, hipStream_t s,
                   bspl_status (*run)(void*, const bspl_tile&, int), void* ctx, bspl_tile* best,
                   float* best_us) {
-    bool have = false;
-    for (const bspl_tile& t : cands) {
+    if (cands.empty()) return fail(BSPL_EUNSUPPORTED, "no candidate tile");
+    std::vector<std::pair<float, size_t>> first;
+    for (size_t i = 0; i < cands.size(); ++i) {
         float us = 0;
-        auto call = [&](int it) { return run(ctx, t, it); };
+        auto call = [&](int it) { return run(ctx, cands[i], it); };
         bspl_status st = time_launch(call, s, 5, &us);
         if (st != BSPL_OK) return st;
-        if (!have || us < *best_us) {
+        first.emplace_back(us, i);
+    }
+    std::sort(first.begin(), first.end());
+    const size_t finalists = std::min<size_t>(4, first.size());
+    for (size_t f = 0; f < finalists; ++f) {
+        const bspl_tile& t = cands[first[f].second];
+        float us = 0;
+        auto call = [&](int it) { return run(ctx, t, it); };
+        bspl_status st = time_launch(call, s, 25, &us);
+        if (st != BSPL_OK) return st;
+        if (f == 0 || us < *best_us) {
             *best = t;
             *best_us = us;
-            have = true;
         }
     }
-    return have ? BSPL_OK : fail(BSPL_EUNSUPPORTED, "no candidate tile");
+    return BSPL_OK;
 }
 
 static bspl_status append_wisdom(const char* path, const char* key, const bspl_tile& t,
