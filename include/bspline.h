@@ -37,11 +37,15 @@
  * Errors common to every evaluation entry point (spline_eval*, the batch
  * plan calls): EINVAL for a NULL table, an unknown kind, npos < 0, ldo < N,
  * a NULL position or output buffer while npos > 0, an invalid tile, or a
- * table of another device; EUNSUPPORTED for npos >= 2^31 or more than 2^31
- * work blocks; EDEVICE when a HIP call fails (the launch itself; faults
- * inside a kernel surface at the next synchronising HIP call, as for any
- * asynchronous work).  npos = 0 is a successful no-op.  After an argument
- * error (EINVAL, EUNSUPPORTED) nothing has been launched.
+ * table of another device; EUNSUPPORTED for npos >= 2^31, more than 2^31 - 1
+ * work blocks, or a split (latency-mode) launch beyond 2^32 - 1 work-items
+ * (spline_launch_query states these limits without a device); EDEVICE when
+ * a HIP call fails (the launch itself; faults inside a kernel surface at the
+ * next synchronising HIP call, as for any asynchronous work).  npos = 0 is a
+ * successful no-op.  Size limits are checked before any HIP call, and after
+ * an argument error (EINVAL, EUNSUPPORTED) nothing has been launched.  A
+ * launch whose workgroups would exceed one dispatch (2^32 - 1 work-items)
+ * runs as a persistent grid of fewer workgroups instead.
  */
 #ifndef BSPLINE_H
 #define BSPLINE_H
@@ -260,6 +264,22 @@ bspl_status spline_eval_vgh(const bspl_table* t, int64_t npos, const double* pos
 bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos,
                         const double* pos, float* v, float* g, float* lh,
                         int64_t ldo, const bspl_tile* tile, void* stream);
+
+/* Host-only: the launch spline_eval makes for a table of this layout (from
+ * spline_layout_query or spline_table_info) at npos positions with this
+ * tile, or with the built-in default tile when tile is NULL (no wisdom is
+ * consulted).  On success *units is the number of work blocks (wx spline
+ * tiles x wy positions; split tiles: wx tiles of one position), *workgroups
+ * the workgroups launched and *threads the threads per workgroup (any of
+ * the three may be NULL).  A grid beyond one dispatch (2^32 - 1 work-items)
+ * is reported as the persistent grid it becomes.  EINVAL for a NULL
+ * layout, a bad kind or dtype, n_splines <= 0, npos < 0 or an invalid tile;
+ * EUNSUPPORTED for npos >= 2^31, more than 2^31 - 1 work blocks or a split
+ * launch beyond 2^32 - 1 work-items.  spline_eval applies exactly these
+ * checks before any HIP call.                                             */
+bspl_status spline_launch_query(const bspl_table_info* layout, bspl_kind kind, int64_t npos,
+                                const bspl_tile* tile, int64_t* units, int64_t* workgroups,
+                                int32_t* threads);
 
 /* Determinant ratios fused with the evaluation (paper, section "QMC and
  * B-spline-based SPOs": after a move of electron e the determinant ratio is

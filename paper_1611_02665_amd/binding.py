@@ -91,6 +91,8 @@ _SIGS = {
     "spline_eval_vgh": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp]),
     "spline_eval": (_int, [_vp, _int, _i64, _vp, _vp, _vp, _vp, _i64, _P(bspl_tile), _vp]),
     "spline_eval_ratio": (_int, [_vp, _int, _i64, _vp, _vp, _i64, _vp, _P(bspl_tile), _vp]),
+    "spline_launch_query": (_int, [_P(bspl_table_info), _int, _i64, _P(bspl_tile), _P(_i64),
+                                   _P(_i64), _P(ctypes.c_int32)]),
     "spline_tile_select": (_int, [_vp, _int, _i64, _P(bspl_tile)]),
     "spline_autotune": (_int, [_vp, _int, _i64, ctypes.c_char_p, _P(bspl_tile), _vp]),
     "spline_wisdom_load": (_int, [ctypes.c_char_p]),
@@ -250,6 +252,24 @@ def spline_eval(table, kind, npos, pos, v, g=None, lh=None, ldo=None, tile=None,
 def spline_eval_ratio(table, kind, npos, pos, ainv, ld_ainv, out, tile=None, stream=None) -> None:
     _check(lib.spline_eval_ratio(table, _enum(kind, KINDS), npos, _ptr(pos), _ptr(ainv), ld_ainv,
                                  _ptr(out), _tile(tile), _stream(stream)), "spline_eval_ratio")
+
+
+def spline_launch_query(layout: dict, kind, npos, tile=None) -> dict:
+    """Host-only launch shape of an evaluation on a table of this layout (a
+    dict from spline_layout_query or spline_table_info): work blocks,
+    workgroups launched and threads per workgroup."""
+    info = bspl_table_info()
+    for k, _ in bspl_table_info._fields_:
+        val = layout[k]
+        if k in ("box", "lattice"):
+            getattr(info, k)[:] = list(val)
+        else:
+            setattr(info, k, val)
+    units, wgs, thr = _i64(), _i64(), ctypes.c_int32()
+    _check(lib.spline_launch_query(ctypes.byref(info), _enum(kind, KINDS), npos, _tile(tile),
+                                   ctypes.byref(units), ctypes.byref(wgs), ctypes.byref(thr)),
+           "spline_launch_query")
+    return {"units": units.value, "workgroups": wgs.value, "threads": thr.value}
 
 
 def spline_tile_select(table, kind, npos) -> bspl_tile:

@@ -116,9 +116,7 @@ void batch_key(const bspl_plan& p, char* buf, size_t n) {
 }
 
 int64_t grid_for(const KernelArgs<kMaxTables>& a, const bspl_tile& t) {
-    int64_t g = a.total_groups;
-    if (t.grid > 0 && t.grid < g) g = t.grid;
-    return std::max<int64_t>(g, 1);
+    return launch_grid(a.total_groups, t.grid, 64 * t.wx * t.wy);
 }
 
 struct TuneCtx {

@@ -49,8 +49,7 @@ bspl_status launch(const void* fn, const KernelArgs<MAXT>& a, const bspl_tile& t
                    hipStream_t s) {
     if (!fn) return fail(BSPL_EINVAL, "no kernel for this dtype/kind/vw");
     if (a.total_groups <= 0) return BSPL_OK;
-    int64_t grid = a.total_groups;
-    if (tile.grid > 0 && tile.grid < grid) grid = tile.grid;
+    const int64_t grid = launch_grid(a.total_groups, tile.grid, 64 * tile.wx * tile.wy);
     dim3 block(64 * tile.wx * tile.wy);
     void* args[] = {const_cast<KernelArgs<MAXT>*>(&a)};
     BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), block, args, 0, s));
@@ -75,6 +74,8 @@ bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
                         (long long)lds, kSplitMaxLds);
         const int64_t blocks = d.npos * (int64_t)d.xgroups;
         if (blocks <= 0) return BSPL_OK;
+        if (blocks > (int64_t)UINT32_MAX / (64 * tile.wx * tile.split))
+            return fail(BSPL_EUNSUPPORTED, "split launch beyond 2^32-1 work-items");
         TableDesc dd = d;
         int wx = tile.wx;
         void* args[] = {&dd, &wx};
@@ -117,8 +118,7 @@ bspl_status launch_ratio(const bspl_table* t, int kind, const TableDesc& d, cons
     if (d.npos <= 0) return BSPL_OK;
     int waves = tile.wx < d.nchunks ? tile.wx : d.nchunks;
     if (waves < 1) waves = 1;
-    int64_t grid = d.npos;
-    if (tile.grid > 0 && tile.grid < grid) grid = tile.grid;
+    const int64_t grid = launch_grid(d.npos, tile.grid, 64 * waves);
     TableDesc dd = d;
     void* args[] = {&dd, const_cast<float**>(&ainv), &ld_ainv, &out};
     BSPL_HIP(hipLaunchKernel(fn, dim3((unsigned)grid), dim3(64 * waves), args, 0, s));

@@ -88,7 +88,38 @@ bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, floa
 bool tile_valid(const bspl_tile& tile, int dtype);
 // The BSPL_TILE environment override: false when unset; *bad when unparsable.
 bool env_tile(bspl_tile* out, bool* bad);
-bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos);
+bspl_tile default_tile(const bspl_table_info& in, int kind, int64_t npos);
+
+// Workgroups a launch of `groups` work blocks of `threads` threads each
+// uses: all of them, or tile.grid persistent ones, and never more than one
+// dispatch holds (2^32 - 1 work-items); the kernels stride over the rest.
+inline int64_t launch_grid(int64_t groups, int32_t grid, int64_t threads) {
+    int64_t g = groups;
+    if (grid > 0 && grid < g) g = grid;
+    const int64_t cap = (int64_t)UINT32_MAX / threads;
+    if (g > cap) g = cap;
+    return g < 1 ? 1 : g;
+}
+
+// The shape of one evaluation launch (host arithmetic only).
+struct LaunchShape {
+    int64_t units;       // work blocks: wx tiles x wy positions (split: wx tiles of one position)
+    int64_t workgroups;  // workgroups launched
+    int32_t threads;     // threads per workgroup
+};
+// EUNSUPPORTED for npos >= 2^31, more than 2^31 - 1 work blocks, or a split
+// launch beyond 2^32 - 1 work-items; the tile must be valid for the dtype.
+bspl_status launch_shape(const bspl_table_info& in, int64_t npos, const bspl_tile& tile,
+                         LaunchShape* out);
+
+// One evaluation, every argument and size checked before any HIP call.
+// tile NULL: the tuned decomposition (tuned = true: spline_tile_select) or
+// the built-in default (tuned = false: no wisdom lookup).  A cell-ordered
+// tile takes its permutation from perm (perm_capacity positions; npos beyond
+// that is EUNSUPPORTED), or from stream-ordered allocation when perm is NULL.
+bspl_status eval_checked(const bspl_table* t, int kind, int64_t npos, const double* pos,
+                         float* v, float* g, float* lh, int64_t ldo, const bspl_tile* tile,
+                         bool tuned, int32_t* perm, int64_t perm_capacity, hipStream_t s);
 
 // Kernel launchers (eval_launch.hip; kernels in eval_device.hpp).
 bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,

@@ -54,11 +54,11 @@ bool tile_valid(const bspl_tile& tile, int dtype) {
 // positions are dense enough to share rows (64 npos / padded points >= 1/2)
 // and the work amortises the ordering pass (npos * N >= 4M); and for a
 // handful of positions the latency mode with 4 wavefronts per unit.
-bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos) {
+bspl_tile default_tile(const bspl_table_info& in, int kind, int64_t npos) {
     (void)kind;
-    const int64_t n = t->info.n_splines;
+    const int64_t n = in.n_splines;
     bspl_tile tile{};
-    tile.vw = t->info.dtype == BSPL_F32 ? 1 : 2;
+    tile.vw = in.dtype == BSPL_F32 ? 1 : 2;
     const int64_t chunks = (n + 64 * tile.vw - 1) / (64 * tile.vw);
     tile.grid = 0;
     tile.order = 0;
@@ -71,7 +71,7 @@ bspl_tile default_tile(const bspl_table* t, int kind, int64_t npos) {
     tile.wx = (int)std::min<int64_t>(4, chunks);
     tile.wy = 1;
     tile.split = 1;
-    const double points = (double)t->info.px * t->info.py * t->info.pz;
+    const double points = (double)in.px * in.py * in.pz;
     if (64.0 * (double)npos >= 0.5 * points && (double)npos * (double)n >= 4194304.0)
         tile.order = 1;
     return tile;
@@ -97,12 +97,51 @@ bool env_tile(bspl_tile* out, bool* bad) {
     return true;
 }
 
+bspl_status launch_shape(const bspl_table_info& in, int64_t npos, const bspl_tile& tile,
+                         LaunchShape* out) {
+    if (npos < 0) return fail(BSPL_EINVAL, "npos %lld < 0", (long long)npos);
+    if (npos > INT32_MAX) return fail(BSPL_EUNSUPPORTED, "npos beyond 2^31-1");
+    if (!tile_valid(tile, in.dtype))
+        return fail(BSPL_EINVAL,
+                    "tile (vw=%d wx=%d wy=%d grid=%d order=%d split=%d) invalid for dtype %d",
+                    tile.vw, tile.wx, tile.wy, tile.grid, tile.order, tile.split, in.dtype);
+    const int64_t nchunks = (in.n_splines + 64 * tile.vw - 1) / (64 * tile.vw);
+    const int64_t xgroups = (nchunks + tile.wx - 1) / tile.wx;
+    LaunchShape ls{};
+    if (tile.split > 1) {
+        // one workgroup per (position, wx tiles): no striding loop
+        ls.threads = 64 * tile.wx * tile.split;
+        ls.units = npos * xgroups;
+        if (ls.units > (int64_t)UINT32_MAX / ls.threads)
+            return fail(BSPL_EUNSUPPORTED,
+                        "split launch of %lld workgroups x %d threads exceeds 2^32-1 work-items",
+                        (long long)ls.units, ls.threads);
+        ls.workgroups = ls.units;
+    } else {
+        ls.threads = 64 * tile.wx * tile.wy;
+        ls.units = xgroups * ((npos + tile.wy - 1) / tile.wy);
+        if (ls.units > INT32_MAX)
+            return fail(BSPL_EUNSUPPORTED, "too many work blocks (%lld)", (long long)ls.units);
+        ls.workgroups = ls.units > 0 ? launch_grid(ls.units, tile.grid, ls.threads) : 0;
+    }
+    *out = ls;
+    return BSPL_OK;
+}
+
 static bool aligned(const void* p, int bytes) {
     return p == nullptr || (reinterpret_cast<uintptr_t>(p) % (uintptr_t)bytes) == 0;
 }
 
 bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, float* v, float* g,
                       float* lh, int64_t ldo, int vw, int wx, int wy, TableDesc* out) {
+    // sizes first (host arithmetic, before any HIP call)
+    {
+        const int64_t nchunks = (t->info.n_splines + 64 * vw - 1) / (64 * vw);
+        const int64_t groups = (nchunks + wx - 1) / wx * ((npos + wy - 1) / wy);
+        if (npos > INT32_MAX) return fail(BSPL_EUNSUPPORTED, "npos beyond 2^31-1");
+        if (groups > INT32_MAX)
+            return fail(BSPL_EUNSUPPORTED, "too many work blocks (%lld)", (long long)groups);
+    }
     // a table's memory belongs to the device it was created on
     int dev = -1;
     BSPL_HIP(hipGetDevice(&dev));
@@ -141,9 +180,6 @@ bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, floa
     d.xgroups = (d.nchunks + wx - 1) / wx;
     const int vb = 4 * vw;
     d.vec_store = (ldo % vw == 0) && aligned(v, vb) && aligned(g, vb) && aligned(lh, vb) ? 1 : 0;
-    const int64_t groups = (int64_t)d.xgroups * ((npos + wy - 1) / wy);
-    if (groups > INT32_MAX)
-        return fail(BSPL_EUNSUPPORTED, "too many work blocks (%lld)", (long long)groups);
     *out = d;
     return BSPL_OK;
 }
@@ -422,13 +458,35 @@ bspl_status spline_tile_select(const bspl_table* t, bspl_kind kind, int64_t npos
         *out = tile;
         return BSPL_OK;
     }
-    *out = default_tile(t, kind, npos);
+    *out = default_tile(t->info, kind, npos);
     return BSPL_OK;
 }
 
-bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const double* pos,
-                        float* v, float* g, float* lh, int64_t ldo, const bspl_tile* tile,
-                        void* stream) {
+bspl_status spline_launch_query(const bspl_table_info* layout, bspl_kind kind, int64_t npos,
+                                const bspl_tile* tile, int64_t* units, int64_t* workgroups,
+                                int32_t* threads) {
+    if (!layout) return fail(BSPL_EINVAL, "layout is NULL");
+    if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
+    if (layout->n_splines <= 0 || layout->dtype < BSPL_F32 || layout->dtype > BSPL_BF16)
+        return fail(BSPL_EINVAL, "layout has n_splines %lld, dtype %d",
+                    (long long)layout->n_splines, (int)layout->dtype);
+    const bspl_tile tl = tile ? *tile : default_tile(*layout, kind, npos);
+    LaunchShape ls;
+    const bspl_status st = launch_shape(*layout, npos, tl, &ls);
+    if (st != BSPL_OK) return st;
+    if (units) *units = ls.units;
+    if (workgroups) *workgroups = ls.workgroups;
+    if (threads) *threads = ls.threads;
+    return BSPL_OK;
+}
+
+}  // extern "C"
+
+namespace bspl {
+
+bspl_status eval_checked(const bspl_table* t, int kind, int64_t npos, const double* pos,
+                         float* v, float* g, float* lh, int64_t ldo, const bspl_tile* tile,
+                         bool tuned, int32_t* perm, int64_t perm_capacity, hipStream_t s) {
     if (!t) return fail(BSPL_EINVAL, "table is NULL");
     if (kind < BSPL_V || kind > BSPL_VGH) return fail(BSPL_EINVAL, "bad kind %d", (int)kind);
     if (npos < 0) return fail(BSPL_EINVAL, "npos %lld < 0", (long long)npos);
@@ -442,22 +500,41 @@ bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const
     bspl_tile tl;
     if (tile) {
         tl = *tile;
-        if (!tile_valid(tl, t->info.dtype))
-            return fail(BSPL_EINVAL,
-                        "tile (vw=%d wx=%d wy=%d grid=%d order=%d split=%d) invalid for dtype %d",
-                        tl.vw, tl.wx, tl.wy, tl.grid, tl.order, tl.split, t->info.dtype);
-    } else {
-        const bspl_status ts = spline_tile_select(t, kind, npos, &tl);
+    } else if (tuned) {
+        const bspl_status ts = spline_tile_select(t, static_cast<bspl_kind>(kind), npos, &tl);
         if (ts != BSPL_OK) return ts;
+    } else {
+        // the environment override, else the built-in default (no wisdom)
+        bool bad = false;
+        if (env_tile(&tl, &bad)) {
+            if (bad || !tile_valid(tl, t->info.dtype))
+                return fail(BSPL_EINVAL, "BSPL_TILE=\"%s\" is not a valid tile for dtype %d",
+                            std::getenv("BSPL_TILE"), (int)t->info.dtype);
+        } else {
+            tl = default_tile(t->info, kind, npos);
+        }
     }
-    TableDesc d;
-    bspl_status st = make_desc(t, npos, pos, v, kind == BSPL_V ? nullptr : g,
-                               kind == BSPL_V ? nullptr : lh, ldo, tl.vw, tl.wx, tl.wy, &d);
+    // every size limit is checked here, before any HIP call
+    LaunchShape ls;
+    bspl_status st = launch_shape(t->info, npos, tl, &ls);
     if (st != BSPL_OK) return st;
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (tl.order > 0 && perm && npos > perm_capacity)
+        return fail(BSPL_EUNSUPPORTED,
+                    "a cell-ordered evaluation of %lld positions needs more than the %lld "
+                    "positions of static scratch memory", (long long)npos,
+                    (long long)perm_capacity);
+    TableDesc d;
+    st = make_desc(t, npos, pos, v, kind == BSPL_V ? nullptr : g, kind == BSPL_V ? nullptr : lh,
+                   ldo, tl.vw, tl.wx, tl.wy, &d);
+    if (st != BSPL_OK) return st;
     if (tl.order == 0) return launch_single(t, kind, d, tl, s);
+    if (perm) {  // the caller's scratch: the permutation is fully rewritten
+        st = launch_order(d, perm, s);
+        if (st != BSPL_OK) return st;
+        d.perm = perm;
+        return launch_single(t, kind, d, tl, s);
+    }
     // cell-ordered: the permutation lives in stream-ordered scratch memory
-    int32_t* perm = nullptr;
     BSPL_HIP(hipMallocAsync((void**)&perm, sizeof(int32_t) * (size_t)npos, s));
     st = launch_order(d, perm, s);
     if (st == BSPL_OK) {
@@ -467,6 +544,17 @@ bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const
     hipError_t e = hipFreeAsync(perm, s);
     if (st == BSPL_OK && e != hipSuccess) return hip_fail(e, "hipFreeAsync(permutation)");
     return st;
+}
+
+}  // namespace bspl
+
+extern "C" {
+
+bspl_status spline_eval(const bspl_table* t, bspl_kind kind, int64_t npos, const double* pos,
+                        float* v, float* g, float* lh, int64_t ldo, const bspl_tile* tile,
+                        void* stream) {
+    return eval_checked(t, kind, npos, pos, v, g, lh, ldo, tile, true, nullptr, 0,
+                        static_cast<hipStream_t>(stream));
 }
 
 bspl_status spline_eval_ratio(const bspl_table* t, bspl_kind kind, int64_t npos,
@@ -490,7 +578,7 @@ bspl_status spline_eval_ratio(const bspl_table* t, bspl_kind kind, int64_t npos,
     } else {
         // two splines per lane and up to 8 wavefronts per position measured
         // best for the ratio kernel on gfx950 (valid for every dtype)
-        tl = default_tile(t, kind, npos);
+        tl = default_tile(t->info, kind, npos);
         tl.vw = 2;
         const int64_t chunks = (t->info.n_splines + 64 * tl.vw - 1) / (64 * tl.vw);
         tl.wx = (int)std::min<int64_t>(8, chunks);

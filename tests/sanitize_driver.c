@@ -132,6 +132,26 @@ static void arguments(void) {
     EXPECT(spline_batch_rebind(NULL, 0, NULL, NULL, NULL, NULL), BSPL_EINVAL);
     EXPECT(spline_batch_plan_tile(NULL, &tile), BSPL_EINVAL);
 
+    bspl_table_info lay;
+    int64_t units = 0, wgs = 0;
+    int32_t thr = 0;
+    bspl_tile t1 = {1, 1, 1, 0, 0, 1}, t8 = {1, 1, 8, 0, 0, 1}, ts = {1, 1, 1, 0, 0, 4};
+    EXPECT(spline_layout_query(4, 4, 4, 700, BSPL_F32, 0, &lay), BSPL_OK);
+    EXPECT(spline_launch_query(&lay, BSPL_VGH, (int64_t)1 << 31, NULL, &units, &wgs, &thr),
+           BSPL_EUNSUPPORTED);
+    EXPECT(spline_launch_query(&lay, BSPL_VGH, ((int64_t)1 << 31) - 1, &t1, &units, &wgs, &thr),
+           BSPL_EUNSUPPORTED);
+    EXPECT(spline_launch_query(&lay, BSPL_VGH, (((int64_t)1 << 31) - 1) / 11, &t8, &units, &wgs,
+                               &thr), BSPL_OK);
+    if (wgs * thr > 4294967295LL) ++failures;
+    EXPECT(spline_launch_query(&lay, BSPL_VGH, 2000000, &ts, NULL, NULL, NULL), BSPL_EUNSUPPORTED);
+    EXPECT(spline_launch_query(&lay, BSPL_VGH, 100, NULL, NULL, NULL, NULL), BSPL_OK);
+    EXPECT(spline_launch_query(&lay, (bspl_kind)-5, 100, NULL, NULL, NULL, NULL), BSPL_EINVAL);
+    EXPECT(spline_launch_query(&lay, BSPL_V, -1, NULL, NULL, NULL, NULL), BSPL_EINVAL);
+    EXPECT(spline_launch_query(NULL, BSPL_V, 1, NULL, NULL, NULL, NULL), BSPL_EINVAL);
+    lay.dtype = 77;
+    EXPECT(spline_launch_query(&lay, BSPL_V, 1, NULL, NULL, NULL, NULL), BSPL_EINVAL);
+
     unsigned layout = 99;
     EXPECT(spline_layout_select(8, 8, 8, 2048, BSPL_F32, BSPL_VGH, 64, NULL, NULL, NULL),
            BSPL_EINVAL);

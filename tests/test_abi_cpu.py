@@ -263,3 +263,54 @@ def test_missing_library_fails_loudly(tmp_path):
                        cwd=tmp_path, capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "ImportError" in r.stderr and "libbspline.so is missing" in r.stderr
+
+
+def test_launch_query_limits_without_a_device():
+    """The size limits spline_eval checks before any HIP call, on a layout
+    from the host-only query: npos >= 2^31, more than 2^31 - 1 work blocks
+    and split launches beyond 2^32 - 1 work-items are EUNSUPPORTED; grids
+    beyond one dispatch become persistent grids."""
+    lay = B.spline_layout_query(4, 4, 4, 700, "f32")
+    # 700 splines at vw = 1: 11 tiles of 64; wx = 1 -> 11 blocks per position
+    for npos, tile in (((1 << 31), None), ((1 << 31), (1, 1, 1, 0, 0, 1)),
+                       ((1 << 31) - 1, (1, 1, 1, 0, 0, 1)), ((1 << 31) - 1, None)):
+        with pytest.raises(B.BsplineError) as e:
+            B.spline_launch_query(lay, "vgh", npos, tile)
+        assert e.value.status == B.BSPL_EUNSUPPORTED, (npos, tile)
+    # the largest batch that fits: 2^31 - 1 blocks of one tile x one position
+    npos = (2**31 - 1) // 11
+    q = B.spline_launch_query(lay, "vgh", npos, (1, 1, 1, 0, 0, 1))
+    assert q["units"] == 11 * npos and q["threads"] == 64
+    assert q["workgroups"] * 64 <= 2**32 - 1 < q["units"] * 64  # persistent grid
+    # eight wavefronts per workgroup: at most 2^32 / 512 workgroups
+    q = B.spline_launch_query(lay, "vgh", npos, (1, 1, 8, 0, 0, 1))
+    assert q["threads"] == 512 and q["workgroups"] == (2**32 - 1) // 512
+    # a requested persistent grid below the cap is kept
+    q = B.spline_launch_query(lay, "v", 1000, (1, 2, 1, 512, 0, 1))
+    assert q == {"units": 6 * 1000, "workgroups": 512, "threads": 128}
+    # split tiles have no striding loop: their work-items are bounded
+    q = B.spline_launch_query(lay, "vgh", 1000, (1, 1, 1, 0, 0, 4))
+    assert q == {"units": 11 * 1000, "workgroups": 11 * 1000, "threads": 256}
+    with pytest.raises(B.BsplineError) as e:
+        B.spline_launch_query(lay, "vgh", (2**32 // 256) // 11 + 1, (1, 1, 1, 0, 0, 4))
+    assert e.value.status == B.BSPL_EUNSUPPORTED
+    # the default tile (NULL): split 4 for a handful of positions, else wx up to 4
+    assert B.spline_launch_query(lay, "vgh", 8)["threads"] == 256
+    q = B.spline_launch_query(lay, "vgh", 100)
+    assert q == {"units": 3 * 100, "workgroups": 300, "threads": 256}
+    # npos = 0: nothing to launch
+    assert B.spline_launch_query(lay, "v", 0, (1, 1, 1, 0, 0, 1))["workgroups"] == 0
+    for bad in ((3, 1, 1, 0, 0, 1), (1, 1, 1, 0, 3, 1), (1, 4, 1, 0, 0, 4)):
+        with pytest.raises(B.BsplineError) as e:
+            B.spline_launch_query(lay, "vgh", 10, bad)
+        assert e.value.status == B.BSPL_EINVAL, bad
+    for kind, npos in ((7, 10), ("vgh", -1)):
+        with pytest.raises(B.BsplineError) as e:
+            B.spline_launch_query(lay, kind, npos)
+        assert e.value.status == B.BSPL_EINVAL
+    assert B.lib.spline_launch_query(None, B.BSPL_V, 1, None, None, None, None) == B.BSPL_EINVAL
+    # FP16 tables take their own vector widths (2, 4, 8)
+    lay16 = B.spline_layout_query(48, 48, 48, 2048, "f16")
+    assert B.spline_launch_query(lay16, "vgh", 4096, (2, 4, 2, 0, 1, 1))["units"] == 4 * 2048
+    with pytest.raises(B.BsplineError):
+        B.spline_launch_query(lay16, "vgh", 4096, (1, 4, 2, 0, 1, 1))

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import synth
-from helpers import assert_close
+from helpers import assert_close, dequantized, normalized_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -170,17 +170,21 @@ CFG4 = [(32, 32, 32, 256), (40, 40, 40, 512), (48, 48, 48, 1152), (64, 64, 64, 2
 CFG4_NPOS = [97, 512, 1500, 3000]
 
 
-def test_config4_batched_sampled():
-    """The four uneven tables of the batched workload in one persistent
-    launch; every position of the small table and 256 sampled positions of
-    each other table are checked against the oracle."""
+@pytest.mark.parametrize("dtype,bound", [("f32", None), ("f16", 2e-3), ("bf16", 5e-3)])
+def test_config4_batched_sampled(dtype, bound):
+    """The four uneven tables of the batched workload in one launch replayed
+    from the plan's graph, with the plan's autotuned tile (as the benchmark
+    runs them); every position of the small table and 256 sampled positions
+    of each other table are checked against the oracle: FP32 tables at 1e-5;
+    FP16/BF16 tables at 1e-5 against the oracle on the dequantised
+    coefficients and within their bound against the original ones."""
     dev = torch.device("cuda")
     handles, coefs = [], []
     try:
         for i, s in enumerate(CFG4):
             c = synth.coef_table(*s, stream=synth.table_stream(i))
             coefs.append(c)
-            handles.append(B.spline_table_create(*s, c, "f32"))
+            handles.append(B.spline_table_create(*s, c, dtype))
         pos = [synth.positions(n, stream=synth.position_stream(i))
                for i, n in enumerate(CFG4_NPOS)]
         pd = [torch.from_numpy(p).to(dev) for p in pos]
@@ -197,10 +201,18 @@ def test_config4_batched_sampled():
             n = CFG4[i][3]
             idx = np.arange(CFG4_NPOS[i]) if CFG4_NPOS[i] <= 256 else \
                 np.sort(rng.choice(CFG4_NPOS[i], 256, replace=False))
-            ref = oracle.evaluate("vgh", coefs[i], pos[i][:, idx])
             got = {k: t.cpu().numpy()[idx][..., :n].astype(np.float64) for k, t in outs[i].items()}
-            assert_close("vgh", got, ref, label=f"config4 table {i}")
-        print("config4 tile", B.spline_batch_plan_tile(plan))
+            if dtype == "f32":
+                assert_close("vgh", got, oracle.evaluate("vgh", coefs[i], pos[i][:, idx]),
+                             label=f"config4 table {i}")
+                continue
+            assert_close("vgh", got, oracle.evaluate("vgh", dequantized(coefs[i], dtype),
+                                                     pos[i][:, idx]),
+                         label=f"config4 {dtype} table {i} vs dequantised")
+            errs = normalized_errors("vgh", got, oracle.evaluate("vgh", coefs[i], pos[i][:, idx]))
+            print(f"config4 {dtype} table {i}", {k: f"{e:.2e}" for k, e in errs.items()})
+            assert max(errs.values()) <= bound, (i, errs)
+        print("config4", dtype, "tile", B.spline_batch_plan_tile(plan))
         B.spline_batch_plan_destroy(plan)
     finally:
         for h in handles:

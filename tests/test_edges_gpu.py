@@ -196,24 +196,3 @@ def test_table_larger_than_device_memory_is_enomem():
         assert_close("vgh", gpu, oracle.evaluate("vgh", coef, pos))
     finally:
         B.spline_table_destroy(h)
-
-
-def test_size_limits_are_unsupported_before_any_launch():
-    """npos >= 2^31, or more than 2^31 - 1 work blocks, is EUNSUPPORTED; the
-    call returns before it launches anything or reads a buffer (the pointers
-    here are placeholders that would fault if dereferenced)."""
-    coef = synth.coef_table(4, 4, 4, 700, stream=197)
-    h = B.spline_table_create(4, 4, 4, 700, coef, "f32")
-    try:
-        fake = 0x1000  # never dereferenced: the size checks come first
-        for npos, tile in (((1 << 31), None), ((1 << 31) - 1, (1, 1, 1, 0, 0, 1)),
-                           ((1 << 31) - 1, None)):
-            with pytest.raises(B.BsplineError) as e:
-                B.spline_eval(h, "vgh", npos, fake, fake, fake, fake, 700, tile=tile)
-            assert e.value.status == B.BSPL_EUNSUPPORTED, (npos, tile)
-        with pytest.raises(B.BsplineError) as e:
-            B.spline_eval_ratio(h, "v", 1 << 31, fake, fake, 700, fake)
-        assert e.value.status == B.BSPL_EUNSUPPORTED
-        torch.cuda.synchronize()  # nothing was queued
-    finally:
-        B.spline_table_destroy(h)
