@@ -281,6 +281,30 @@ bspl_status spline_launch_query(const bspl_table_info* layout, bspl_kind kind, i
                                 const bspl_tile* tile, int64_t* units, int64_t* workgroups,
                                 int32_t* threads);
 
+/* spline_eval without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, checks, kernels and results as
+ * spline_eval, with two differences:
+ *  - a cell-ordered tile (order 1 or 2) keeps its permutation in a static
+ *    device array of BSPL_NOALLOC_MAX_POSITIONS int32 entries (4 MiB, held
+ *    by each device the library runs on until the process ends) instead of
+ *    stream-ordered scratch memory; npos beyond that limit with an ordered
+ *    tile is EUNSUPPORTED, checked before any HIP call.  Unordered tiles use
+ *    no scratch memory at all.
+ *  - tile NULL takes the BSPL_TILE override or the built-in default
+ *    decomposition (spline_tile_select without the wisdom cache).
+ * The call makes no hipMalloc, hipFree or other allocating call.  Every
+ * ordered call on one device shares that device's array, and each call
+ * rewrites the part it uses, so ordered calls that overlap in time on one
+ * device (different streams, or host threads without ordering between
+ * them) race and give undefined results; calls on one stream are ordered
+ * by the stream.  The first call on a device looks up the array's device
+ * address (hipGetSymbolAddress) with that device current.                 */
+#define BSPL_NOALLOC_MAX_POSITIONS (1 << 20)
+bspl_status spline_eval_noalloc(const bspl_table* t, bspl_kind kind, int64_t npos,
+                                const double* pos, float* v, float* g, float* lh,
+                                int64_t ldo, const bspl_tile* tile, void* stream);
+
 /* Determinant ratios fused with the evaluation (paper, section "QMC and
  * B-spline-based SPOs": after a move of electron e the determinant ratio is
  * the sum over orbitals n of phi_n(r_e) times the inverse-matrix entry

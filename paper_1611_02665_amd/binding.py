@@ -32,6 +32,7 @@ BSPL_COEFS_DEVICE = 0x2
 BSPL_COEFS_GRID_VALUES = 0x4
 BSPL_LAYOUT_BLOCKED = 0x8
 MAX_TABLES = 16
+NOALLOC_MAX_POSITIONS = 1 << 20
 
 DTYPES = {"f32": BSPL_F32, "f16": BSPL_F16, "bf16": BSPL_BF16}
 KINDS = {"v": BSPL_V, "vgl": BSPL_VGL, "vgh": BSPL_VGH}
@@ -90,6 +91,8 @@ _SIGS = {
     "spline_eval_vgl": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp]),
     "spline_eval_vgh": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, _i64, _vp]),
     "spline_eval": (_int, [_vp, _int, _i64, _vp, _vp, _vp, _vp, _i64, _P(bspl_tile), _vp]),
+    "spline_eval_noalloc": (_int, [_vp, _int, _i64, _vp, _vp, _vp, _vp, _i64, _P(bspl_tile),
+                                   _vp]),
     "spline_eval_ratio": (_int, [_vp, _int, _i64, _vp, _vp, _i64, _vp, _P(bspl_tile), _vp]),
     "spline_launch_query": (_int, [_P(bspl_table_info), _int, _i64, _P(bspl_tile), _P(_i64),
                                    _P(_i64), _P(ctypes.c_int32)]),
@@ -249,6 +252,13 @@ def spline_eval(table, kind, npos, pos, v, g=None, lh=None, ldo=None, tile=None,
                            _ptr(lh), ldo, _tile(tile), _stream(stream)), "spline_eval")
 
 
+def spline_eval_noalloc(table, kind, npos, pos, v, g=None, lh=None, ldo=None, tile=None,
+                        stream=None) -> None:
+    _check(lib.spline_eval_noalloc(table, _enum(kind, KINDS), npos, _ptr(pos), _ptr(v), _ptr(g),
+                                   _ptr(lh), ldo, _tile(tile), _stream(stream)),
+           "spline_eval_noalloc")
+
+
 def spline_eval_ratio(table, kind, npos, pos, ainv, ld_ainv, out, tile=None, stream=None) -> None:
     _check(lib.spline_eval_ratio(table, _enum(kind, KINDS), npos, _ptr(pos), _ptr(ainv), ld_ainv,
                                  _ptr(out), _tile(tile), _stream(stream)), "spline_eval_ratio")
@@ -332,3 +342,4 @@ def spline_batch_plan_tile(plan) -> bspl_tile:
 
 def spline_batch_plan_destroy(plan) -> None:
     _check(lib.spline_batch_plan_destroy(plan), "spline_batch_plan_destroy")
+

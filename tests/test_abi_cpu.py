@@ -9,13 +9,20 @@ import pytest
 
 from paper_1611_02665_amd import binding as B
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "bspline.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include")
+HEADER = os.path.join(INCLUDE, "bspline.h")
 
 
 def _declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(spline_\w+)\s*\(", text)))
+    """Every spline_* function declared in include/*.h."""
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if not f.endswith(".h"):
+            continue
+        text = open(os.path.join(INCLUDE, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(spline_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_every_declared_function_is_exported_and_bound():
@@ -210,6 +217,8 @@ def test_null_handles():
     assert B.lib.spline_batch_launch(None, None) == B.BSPL_EINVAL
     assert B.lib.spline_batch_rebind(None, 0, None, None, None, None) == B.BSPL_EINVAL
     assert B.lib.spline_batch_plan_tile(None, ctypes.byref(t)) == B.BSPL_EINVAL
+    assert B.lib.spline_eval_noalloc(None, 2, 1, None, None, None, None, 1, None,
+                                     None) == B.BSPL_EINVAL
 
 
 def test_batch_plan_argument_checks():
