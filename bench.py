@@ -123,6 +123,56 @@ def timed(torch, fn, steps, warmup):
     return a.elapsed_time(b) / steps  # ms per call
 
 
+def timed_steps(torch, fn, nb, steps, warmup):
+    """Timed region of exactly `steps` steps, each one launch per batch of the
+    nb batches (fn(i) launches batch i % nb), with an event after every
+    step.  Returns (mean ms per step over the region, per-step ms list)."""
+    for i in range(warmup * nb):
+        fn(i)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for s in range(steps):
+        for b in range(nb):
+            fn(s * nb + b)
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    per = [ev[s].elapsed_time(ev[s + 1]) for s in range(steps)]
+    return ev[0].elapsed_time(ev[steps]) / steps, per
+
+
+def memory_ceiling(torch, B, footprints_gib=(1, 16)):
+    """Best bandwidth of the streaming probe (spline_stream_probe: 6 reads of
+    16 bytes per 16-byte write, the evaluation's 86/14 read/write mix) over
+    its launch variants, at each footprint (reads plus writes)."""
+    stream = torch.cuda.current_stream().cuda_stream
+    out = {}
+    for gib in footprints_gib:
+        units = (gib << 30) // 112 // 64 * 64
+        src = torch.ones(6 * units * 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty(units * 4, dtype=torch.int32, device="cuda")
+        best = None
+        for flags in (0, B.BSPL_PROBE_NT_STORES, B.BSPL_PROBE_CHUNKED,
+                      B.BSPL_PROBE_CHUNKED | B.BSPL_PROBE_NT_STORES):
+            for u in (1, 2, 4):
+                for grid in (0, 2048, 8192):
+                    ms = timed(torch, lambda i: B.spline_stream_probe(src, dst, units, u, grid,
+                                                                      flags, stream),
+                               20 if gib == 1 else 5, 2)
+                    gbs = 112 * units / (ms * 1e-3) / 1e9
+                    if best is None or gbs > best[0]:
+                        best = (gbs, u, grid, flags)
+        torch.cuda.synchronize()
+        if int(dst[0].item()) != 6:
+            raise RuntimeError("stream probe wrote a wrong sum")
+        out[f"mix_86_14_{gib}GiB"] = {"gbs": best[0], "per_lane": best[1], "grid": best[2],
+                                      "nt_stores": bool(best[3] & B.BSPL_PROBE_NT_STORES),
+                                      "chunked": bool(best[3] & B.BSPL_PROBE_CHUNKED)}
+        del src, dst
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_probe(torch, nbytes=1 << 30, reps=20):
     """Plain device-to-device copy of known size (counter calibration and the
     measured copy bandwidth)."""
@@ -135,8 +185,9 @@ def copy_probe(torch, nbytes=1 << 30, reps=20):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=125,
+                    help="timed steps; a step is one launch on each of the 16 batches")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed steps before them")
     ap.add_argument("--profile", action="store_true", help="headline kernel only")
     ap.add_argument("--blocked", action="store_true",
                     help="profiling: a spline-blocked table instead of the plain one")
@@ -224,9 +275,10 @@ def main(argv=None):
         B._check(B.lib.spline_eval(t32, B.BSPL_VGH, npos, pp[i % nbatch], vp, gp, hp, ldo, tref,
                                    stream), "spline_eval")
 
-    steps = 20 if args.profile else args.steps
-    warmup = 5 if args.profile else args.warmup
-    ms = timed(torch, vgh_step, steps, warmup)
+    steps = 2 if args.profile else args.steps
+    warmup = 1 if args.profile else args.warmup
+    ms_step, per_step = timed_steps(torch, vgh_step, nbatch, steps, warmup)
+    ms = ms_step / nbatch  # mean launch duration over the timed region
     evals = npos * NSPL
     value = evals / (ms * 1e-3)
     alg_bytes = A.batch_bytes("vgh", args.dtype, npos, NSPL)
@@ -235,6 +287,9 @@ def main(argv=None):
     if args.profile:
         B.spline_table_destroy(t32)
         return 0
+    per_step.sort()
+    med_step = per_step[len(per_step) // 2] if len(per_step) % 2 else \
+        0.5 * (per_step[len(per_step) // 2 - 1] + per_step[len(per_step) // 2])
 
     traffic = read_traffic(alg_bytes, tile)
     line = {
@@ -244,7 +299,9 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": steps,
         "warmup": warmup,
-        "ms_per_step": ms,
+        "ms_per_step": ms_step,
+        "median_ms_per_step": med_step,
+        "us_per_launch": ms * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -252,7 +309,9 @@ def main(argv=None):
         "data": "synthetic",
         "config": {
             "workload": "eval_vgh, 48^3 periodic grid (51^3 padded) x N=2048 FP32 table "
-                        "(1.09 GB), 512 uniform positions per batch, 16 batches cycled",
+                        "(1.09 GB), 512 uniform positions per batch; one step = one launch "
+                        "on each of 16 pre-generated batches (8192 positions)",
+            "launches_per_step": nbatch,
             "grid": list(GRID), "n_splines": NSPL, "npos": NPOS, "kernel": "eval_vgh",
             "table_dtype": "f32", "tile": list(tile.as_tuple()), "tile_source": tile_source,
         },
@@ -281,6 +340,9 @@ def main(argv=None):
     line["gpu_clocks"] = gpu_clocks()
     extra = {}
     keep = {}
+    # the extras time single launches: warm-up launches and repetitions
+    warmup = max(10, warmup * nbatch)
+    steps = max(200, steps * nbatch // 4)
     if not args.no_extras:
         # V and VGL on the same table and batches
         tile_v = B.spline_autotune(t32, "v", NPOS)
@@ -362,9 +424,12 @@ def main(argv=None):
                                       "us_per_launch": ms_r * 1e3, "tile": list(rt),
                                       "alg_bytes_per_launch": rb,
                                       "hbm_gbs": rb / (ms_r * 1e-3) / 1e9}
-        copy_gbs, _ = copy_probe(torch)
-        extra["copy_gbs_measured"] = copy_gbs
-        line["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs
+        # the practical memory ceiling with the kernel's read/write mix
+        ceil = memory_ceiling(torch, B)
+        extra["memory_ceiling"] = ceil
+        line["roofline"]["measured_ceiling_gbs"] = ceil["mix_86_14_1GiB"]["gbs"]
+        line["roofline"]["frac_of_measured_ceiling"] = achieved / ceil["mix_86_14_1GiB"]["gbs"]
+        log("[bench] memory ceiling probe done")
         extra["precision"] = precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup)
         log("[bench] precision extra done")
         extra["batched"] = batched_extra(torch, B, A, synth, steps, warmup, keep)
@@ -375,9 +440,13 @@ def main(argv=None):
         log("[bench] large-table extra done")
         line["extra"] = extra
 
+    samples = None if args.no_cpu else gpu_samples(torch, np, B, synth, coef, t32)
     B.spline_table_destroy(t32)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(np, synth, coef)
+        line["cpu_baseline"]["error_vs_oracle"] = oracle_errors(
+            np, coef, samples, sample_positions(np, synth))
+        log("[bench] oracle errors done")
         line["cpu_baseline"]["per_config"] = cpu_oracle_configs(np, synth, coef,
                                                                keep.get("cfg4_coefs"))
     print(json.dumps(line), flush=True)
@@ -583,16 +652,49 @@ def gpu_clocks():
     return {k: v for k, v in card.items() if "clock" in k.lower() or "clk" in k.lower()}
 
 
+def interleaved(torch, fns, k, reps=25):
+    """Per-launch ms of each of the callables fns[l](i), timed back to back:
+    rep r runs k launches of every layout in turn, rotating which goes first.
+    Returns the per-rep times, one list per callable."""
+    n = len(fns)
+    for f in fns:
+        for i in range(3):
+            f(i)
+    torch.cuda.synchronize()
+    times = [[] for _ in range(n)]
+    for r in range(reps):
+        order = [(r + j) % n for j in range(n)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        ev[0].record()
+        for j, l in enumerate(order):
+            for i in range(k):
+                fns[l](r * k + i)
+            ev[j + 1].record()
+        torch.cuda.synchronize()
+        for j, l in enumerate(order):
+            times[l].append(ev[j].elapsed_time(ev[j + 1]) / k)
+    return times
+
+
+def median(xs):
+    xs = sorted(xs)
+    m = len(xs) // 2
+    return xs[m] if len(xs) % 2 else 0.5 * (xs[m - 1] + xs[m])
+
+
 def layout_extra(torch, B, synth, coef, t32, steps, warmup):
     """Plain against spline-blocked tables (the paper's AoSoA sub-tables), each
-    at its own autotuned tile: FP32 VGH on the headline's 512-position
-    batches and FP16 VGH on 4096 positions, with the layout that
-    spline_layout_select picks from those timings."""
+    at its own autotuned tile, timed back to back on the same batches (25
+    reps, alternating which layout goes first): FP32 VGH on the headline's
+    512-position batches and FP16 VGH on 4096 positions, with the layout that
+    spline_layout_select picks."""
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
     res = {"workload": "eval_vgh on the 48^3 x N=2048 coefficients; blocks of 256 (FP32) or "
                        "512 (FP16) splines, [N/B][51][51][51][B]; uniform positions, "
-                       "batches cycled"}
+                       "batches cycled; 25 interleaved reps, medians",
+           "rule": "the selector keeps plain unless blocked is faster by more than "
+                   "max(3 %, 2 x 1.4826 x MAD of the per-rep time ratio)"}
     for dt, npos, nb in (("f32", NPOS, NBATCH), ("f16", 4096, 4)):
         batches = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0),
                                                     batch=b)).to(dev) for b in range(nb)]
@@ -600,19 +702,31 @@ def layout_extra(torch, B, synth, coef, t32, steps, warmup):
         g = torch.empty(npos, 3, NSPL, device=dev)
         h = torch.empty(npos, 6, NSPL, device=dev)
         row = {}
+        tabs, fns = [], []
         for name, flags in (("plain", 0), ("blocked", B.BSPL_LAYOUT_BLOCKED)):
             t = t32 if (dt == "f32" and flags == 0) else B.spline_table_create(
                 *GRID, NSPL, coef, dt, flags=flags)
             tile = B.spline_autotune(t, "vgh", npos)
-            ms = timed(torch, lambda i: B.spline_eval(t, "vgh", npos, batches[i % nb], v, g, h,
-                                                      NSPL, tile=tile, stream=stream),
-                       max(100, steps // 4), warmup)
+            row[f"{name}_tile"] = list(tile.as_tuple())
+            tabs.append(t)
+            fns.append(lambda i, t=t, tile=tile: B.spline_eval(
+                t, "vgh", npos, batches[i % nb], v, g, h, NSPL, tile=tile, stream=stream))
+        k = 16 if npos <= NPOS else 4
+        times = interleaved(torch, fns, k)
+        ratios = [b / p for p, b in zip(times[0], times[1])]
+        r_med = median(ratios)
+        noise = 1.4826 * median([abs(x - r_med) for x in ratios])
+        for l, name in enumerate(("plain", "blocked")):
+            ms = median(times[l])
             row[f"{name}_us_per_launch"] = ms * 1e3
             row[f"{name}_evals_per_s"] = npos * NSPL / (ms * 1e-3)
-            row[f"{name}_tile"] = list(tile.as_tuple())
+        for t in tabs:
             if t != t32:
                 B.spline_table_destroy(t)
-        row["blocked_over_plain_time"] = row["blocked_us_per_launch"] / row["plain_us_per_launch"]
+        row["blocked_over_plain_time"] = r_med
+        row["ratio_noise"] = noise
+        row["faster"] = "blocked" if r_med < 1.0 else "plain"
+        row["difference_within_margin"] = abs(1.0 - r_med) <= max(0.03, 2.0 * noise)
         sel = B.spline_layout_select(*GRID, NSPL, dt, "vgh", npos)
         row["selected"] = "blocked" if sel == B.BSPL_LAYOUT_BLOCKED else "plain"
         res[f"{dt}_vgh_{npos}pos"] = row
@@ -721,6 +835,8 @@ def sweep_mode(torch, B, A, synth):
                               "npos": npos, "kernel": "eval_" + kind, "us_per_launch": ms * 1e3,
                               "evals_per_s": npos * n / (ms * 1e-3),
                               "hbm_gbs": A.batch_bytes(kind, "f32", npos, n) / (ms * 1e-3) / 1e9,
+                              "frac_of_peak": A.batch_bytes(kind, "f32", npos, n)
+                              / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                               "tile": list(tile.as_tuple())}), flush=True)
             if n == 2048 and kind == "vgh":
                 # tile-width study: splines per workgroup 64*vw*wx, one position row
@@ -737,6 +853,31 @@ def sweep_mode(torch, B, A, synth):
                                           "splines_per_workgroup": 64 * vw * wx,
                                           "us_per_launch": ms * 1e3,
                                           "evals_per_s": npos * n / (ms * 1e-3)}), flush=True)
+        if n <= 1024:
+            # many walker batches per launch: the 16 batches of 512 positions
+            # as one batch plan (16 entries of the same table), issued as
+            # direct launches and as a graph replay
+            outs = [(torch.empty(npos, n, device=dev), torch.empty(npos, 3, n, device=dev),
+                     torch.empty(npos, 6, n, device=dev)) for _ in range(NBATCH)]
+            plan = B.spline_batch_plan_create([t] * NBATCH, [npos] * NBATCH, "vgh", batches,
+                                              [o[0] for o in outs], [o[1] for o in outs],
+                                              [o[2] for o in outs], [n] * NBATCH,
+                                              stream=stream)
+            ms_d = timed(torch, lambda i: B.spline_batch_launch(plan, stream), 100, 10)
+            ms_g = timed(torch, lambda i: B.spline_batch_execute(plan, stream), 100, 10)
+            alg = NBATCH * A.batch_bytes("vgh", "f32", npos, n)
+            print(json.dumps({"sweep": "n_splines_batched", "grid": list(GRID), "n_splines": n,
+                              "npos": npos, "walker_batches_per_launch": NBATCH,
+                              "kernel": "eval_vgh", "us_per_launch": ms_d * 1e3,
+                              "evals_per_s": NBATCH * npos * n / (ms_d * 1e-3),
+                              "hbm_gbs": alg / (ms_d * 1e-3) / 1e9,
+                              "frac_of_peak": alg / (ms_d * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "us_per_graph_replay": ms_g * 1e3,
+                              "graph_evals_per_s": NBATCH * npos * n / (ms_g * 1e-3),
+                              "tile": list(B.spline_batch_plan_tile(plan).as_tuple())}),
+                  flush=True)
+            B.spline_batch_plan_destroy(plan)
+            del outs
         B.spline_table_destroy(t)
         # the same table stored as FP16 (per-spline scales), VGH
         coef = synth.coef_table(*GRID, n, stream=synth.table_stream(0))
@@ -790,6 +931,99 @@ def cpu_baseline(np, synth, coef, budget_cpu_s=12.0, max_batches=64):
             "sample": f"eval_vgh FP64 oracle (C, OpenMP over positions), {b} batches x "
                       f"{NPOS} positions x N={NSPL} of the same 48^3 table, {wall:.2f} s wall",
             "cpu_model": cpu, "nproc": os.cpu_count(), "single_core_value": one}
+
+
+ACC_PER_BATCH = 16  # positions sampled from each timed batch for the error report
+ERR_BOUND = {"f32": 1e-5, "f16": 2e-3, "bf16": 5e-3}
+COMP_NAMES = {"vgh": ["v", "gx", "gy", "gz", "hxx", "hxy", "hxz", "hyy", "hyz", "hzz"],
+              "vgl": ["v", "gx", "gy", "gz", "l"]}
+
+
+def sample_positions(np, synth):
+    """The first ACC_PER_BATCH positions of each of the 16 timed batches."""
+    return np.ascontiguousarray(np.concatenate(
+        [synth.positions(NPOS, stream=synth.position_stream(0), batch=b)[:, :ACC_PER_BATCH]
+         for b in range(NBATCH)], axis=1))
+
+
+def gpu_samples(torch, np, B, synth, coef, t32):
+    """GPU outputs of VGH and VGL at the sampled positions for the FP32, FP16
+    and BF16 tables (each with its tuned or default tile), as host arrays."""
+    dev = torch.device("cuda")
+    pos = sample_positions(np, synth)
+    m = pos.shape[1]
+    p = torch.from_numpy(pos).to(dev)
+    v = torch.empty(m, NSPL, device=dev)
+    g = torch.empty(m, 3, NSPL, device=dev)
+    lh = torch.empty(m, 6, NSPL, device=dev)
+    out = {}
+    for dt in ("f32", "f16", "bf16"):
+        t = t32 if dt == "f32" else B.spline_table_create(*GRID, NSPL, coef, dt)
+        for kind in ("vgh", "vgl"):
+            B.spline_eval(t, kind, m, p, v, g, lh, NSPL)
+            torch.cuda.synchronize()
+            comps = [v.cpu().numpy()] + [g[:, c].cpu().numpy() for c in range(3)]
+            if kind == "vgh":
+                comps += [lh[:, c].cpu().numpy() for c in range(6)]
+            else:
+                comps.append(lh.view(-1)[:m * NSPL].cpu().numpy().reshape(m, NSPL))
+            out[(dt, kind)] = [c.astype(np.float64) for c in comps]
+        if dt != "f32":
+            B.spline_table_destroy(t)
+    return out
+
+
+def dequantized(np, coef, dt):
+    """The values an FP16/BF16 table stores, restated on the host from the
+    storage rule: per-spline scale s_n = 2^ceil(log2 max|c_n|) (1 for an
+    all-zero spline) and the code c/s_n rounded to nearest-even."""
+    m = np.abs(coef.reshape(-1, coef.shape[-1])).max(axis=0).astype(np.float64)
+    sc = np.ones_like(m)
+    sc[m > 0] = 2.0 ** np.ceil(np.log2(m[m > 0]))
+    x = (coef / sc.astype(np.float32)).astype(np.float32)
+    if dt == "f16":
+        q = x.astype(np.float16).astype(np.float32)
+    else:
+        b = x.view(np.uint32).astype(np.uint64)
+        q = (((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16).astype(np.uint32).view(np.float32)
+    return q * sc.astype(np.float32)
+
+
+def oracle_errors(np, coef, samples, pos):
+    """Error of every output component of the GPU samples against the FP64
+    oracle: max |gpu - oracle| / max |oracle| per component, with the oracle
+    on the original coefficients and, for FP16/BF16, also on the values the
+    table stores (which isolates the kernel from the storage rounding)."""
+    import oracle
+
+    def errs(kind, got, ref):
+        keys = ["v", ("g", 0), ("g", 1), ("g", 2)]
+        keys += [("h", c) for c in range(6)] if kind == "vgh" else ["l"]
+        out = {}
+        for name, k, a in zip(COMP_NAMES[kind], keys, got):
+            r = ref[k] if isinstance(k, str) else ref[k[0]][:, k[1]]
+            out[name] = float(np.abs(a - r).max() / np.abs(r).max())
+        return out
+
+    res = {"reference": "FP64 oracle (C)", "positions": int(pos.shape[1]),
+           "sample": f"the first {ACC_PER_BATCH} positions of each of the {NBATCH} timed "
+                     f"512-position batches, all {NSPL} splines",
+           "normalisation": "per component: max |gpu - oracle| / max |oracle|",
+           "bound": dict(ERR_BOUND)}
+    refs = {kind: oracle.evaluate(kind, coef, pos) for kind in ("vgh", "vgl")}
+    for dt in ("f32", "f16", "bf16"):
+        row = {}
+        deq = dequantized(np, coef, dt) if dt != "f32" else None
+        for kind in ("vgh", "vgl"):
+            row[kind] = errs(kind, samples[(dt, kind)], refs[kind])
+            if deq is not None:
+                row[kind + "_vs_stored_values"] = errs(kind, samples[(dt, kind)],
+                                                       oracle.evaluate(kind, deq, pos))
+        row["max"] = max(max(row[k].values()) for k in ("vgh", "vgl"))
+        row["within_bound"] = row["max"] <= ERR_BOUND[dt]
+        res[dt] = row
+        del deq
+    return res
 
 
 def cpu_oracle_configs(np, synth, coef48, cfg4_coefs):

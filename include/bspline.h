@@ -352,11 +352,16 @@ bspl_status spline_autotune(const bspl_table* t, bspl_kind kind, int64_t npos,
  * size, section "Experiments and Results").  Decides between the plain and
  * the spline-blocked layout for tables of this shape, dtype and kind at
  * this batch size, on box cells, and returns 0 or BSPL_LAYOUT_BLOCKED in
- * *layout.  It compares the best tile times that the wisdom cache holds
- * for both layouts; a layout without a timed entry is autotuned on a
- * temporary zero-coefficient table of the real shape (timing does not
- * depend on the values), which is recorded in the cache and appended to
- * wisdom_path when that is not NULL.  Shapes of at most one block
+ * *layout.  Both layouts are built as temporary tables of the real shape
+ * with random coefficients (timing does not depend on them), each runs at its
+ * best tile (from the wisdom cache, else autotuned, recorded in the cache
+ * and appended to wisdom_path when that is not NULL), and the two are
+ * timed back to back on the same random positions, alternating which goes
+ * first, 25 times.  The blocked layout is chosen only when the median of
+ * the per-rep time ratio blocked/plain lies below 1 by more than twice its
+ * spread (1.4826 x the median absolute deviation) and by at least 3 %
+ * (the spread between two allocations of one layout);
+ * otherwise the plain layout is kept.  Shapes of at most one block
  * (n_splines <= 256 for F32, 512 for F16/BF16) return 0 at once.  Needs
  * device memory for one table of each layout plus the unpadded
  * coefficients; synchronizes the stream.  Errors as spline_table_create

@@ -33,6 +33,8 @@ BSPL_COEFS_GRID_VALUES = 0x4
 BSPL_LAYOUT_BLOCKED = 0x8
 MAX_TABLES = 16
 NOALLOC_MAX_POSITIONS = 1 << 20
+BSPL_PROBE_NT_STORES = 0x1
+BSPL_PROBE_CHUNKED = 0x2
 
 DTYPES = {"f32": BSPL_F32, "f16": BSPL_F16, "bf16": BSPL_BF16}
 KINDS = {"v": BSPL_V, "vgl": BSPL_VGL, "vgh": BSPL_VGH}
@@ -108,6 +110,8 @@ _SIGS = {
     "spline_batch_rebind": (_int, [_vp, _int, _vp, _vp, _vp, _vp]),
     "spline_batch_plan_tile": (_int, [_vp, _P(bspl_tile)]),
     "spline_batch_plan_destroy": (_int, [_vp]),
+    "spline_stream_probe": (_int, [_vp, _vp, _i64, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -343,3 +347,9 @@ def spline_batch_plan_tile(plan) -> bspl_tile:
 def spline_batch_plan_destroy(plan) -> None:
     _check(lib.spline_batch_plan_destroy(plan), "spline_batch_plan_destroy")
 
+
+def spline_stream_probe(src, dst, units, per_lane=1, grid=0, flags=0, stream=None) -> None:
+    """Measurement helper (bspline_probe.h): 6 reads of 16 bytes per 16-byte
+    write; src holds 6 * units words, dst units words."""
+    _check(lib.spline_stream_probe(_ptr(src), _ptr(dst), units, per_lane, grid, flags,
+                                   _stream(stream)), "spline_stream_probe")

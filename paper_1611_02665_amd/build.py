@@ -16,7 +16,7 @@ OBJDIR = os.path.join(PKG, "_build")
 
 SOURCES = ["eval_f32.hip", "eval_f16.hip", "eval_bf16.hip", "eval_launch.hip", "table.cpp",
            "layout_kernels.hip", "order_kernels.hip", "fit_kernels.hip", "autotune.cpp",
-           "batch.cpp", "noalloc.hip"]
+           "batch.cpp", "noalloc.hip", "stream_probe.hip"]
 ARCH = os.environ.get("BSPL_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

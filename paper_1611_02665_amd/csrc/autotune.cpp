@@ -8,6 +8,7 @@
 // table at the real batch size; the winner is cached per
 // (arch, dtype, kind, N, grid, npos bucket) and can be written to a text file.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -86,6 +87,18 @@ __global__ void random_positions(double* pos, int64_t npos, double lx, double ly
     const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
     const int64_t d = i / npos;
     pos[i] = u * (d == 0 ? lx : (d == 1 ? ly : lz));
+}
+
+// Coefficients uniform in (-1, 1) from a counter hash, for tables that are
+// built only to be timed.
+__global__ void random_coefs(float* c, int64_t n, uint64_t salt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t z = (uint64_t)i * 0x9E3779B97F4A7C15ull + salt;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    c[i] = (float)((double)(z >> 40) * (2.0 / 16777216.0) - 1.0);
 }
 
 }  // namespace
@@ -271,6 +284,93 @@ bspl_status run_single(void* vctx, const bspl_tile& tile, int it) {
                        c->out[0], c->out[1], c->out[2], c->ldo, &tile, c->s);
 }
 
+// Layout selection: the plain and the spline-blocked table of one shape,
+// each at its best tile, timed back to back on the same positions.  Rep r
+// times k launches of one layout, then k of the other (plain first on even
+// reps, blocked first on odd ones), and the per-rep ratio blocked / plain
+// is summarised by its median and its spread (1.4826 * median absolute
+// deviation, the standard deviation of normal noise).  The spread of one
+// race misses the difference between two allocations of the same layout
+// (which pages the table lands on), measured at up to 2 % on MI355X, so the
+// blocked layout must also win by at least 3 %.
+constexpr int kLayoutReps = 25;
+constexpr float kLayoutMinMargin = 0.03f;
+
+struct LayoutRace {
+    float* coefs = nullptr;
+    bspl_table* t[2] = {nullptr, nullptr};
+    bspl_tile tile[2] = {};
+    void* mem = nullptr;
+
+    bspl_status run(int kind, int64_t npos, hipStream_t s, float* ratio, float* noise) {
+        const int ncomp = kind == BSPL_V ? 1 : (kind == BSPL_VGL ? 5 : 10);
+        const int64_t ldo = t[0]->info.n_padded;
+        const size_t pos_bytes = (sizeof(double) * 3 * (size_t)npos + 255) / 256 * 256;
+        const size_t out_bytes = sizeof(float) * (size_t)npos * (size_t)ldo;
+        BSPL_HIP(hipMalloc(&mem, 4 * pos_bytes + (size_t)ncomp * out_bytes));
+        char* m = static_cast<char*>(mem);
+        double* pos[4];
+        for (int b = 0; b < 4; ++b) pos[b] = reinterpret_cast<double*>(m + b * pos_bytes);
+        float* v = reinterpret_cast<float*>(m + 4 * pos_bytes);
+        float* g = v + (size_t)npos * ldo;
+        float* lh = g + (size_t)3 * npos * ldo;
+        for (int b = 0; b < 4; ++b) {
+            const bspl_status st = fill_random_positions(pos[b], npos, t[0]->info.box,
+                                                         0x1a7000ull + b, s);
+            if (st != BSPL_OK) return st;
+        }
+        auto launches = [&](int l, int k, int it0) {
+            for (int i = 0; i < k; ++i) {
+                const bspl_status st = spline_eval(t[l], static_cast<bspl_kind>(kind), npos,
+                                                   pos[(it0 + i) & 3], v, g, lh, ldo, &tile[l], s);
+                if (st != BSPL_OK) return st;
+            }
+            return BSPL_OK;
+        };
+        // launches per timing: about 300 us of work (at least 2)
+        float us0 = 0.f;
+        bspl_status st = time_launch([&](int it) { return launches(0, 1, it); }, s, 5, &us0);
+        if (st != BSPL_OK) return st;
+        const int k = std::min(64, std::max(2, (int)(300.f / std::max(us0, 1.f)) + 1));
+        hipEvent_t ev[3];
+        for (int i = 0; i < 3; ++i) BSPL_HIP(hipEventCreate(&ev[i]));
+        std::vector<float> r;
+        for (int rep = 0; rep < kLayoutReps && st == BSPL_OK; ++rep) {
+            const int first = rep & 1;
+            float ms[2] = {0.f, 0.f};
+            (void)hipEventRecord(ev[0], s);
+            st = launches(first, k, 2 * rep);
+            (void)hipEventRecord(ev[1], s);
+            if (st == BSPL_OK) st = launches(1 - first, k, 2 * rep);
+            (void)hipEventRecord(ev[2], s);
+            const hipError_t e = hipEventSynchronize(ev[2]);
+            if (st == BSPL_OK && e != hipSuccess) st = hip_fail(e, "layout timing");
+            if (st != BSPL_OK) break;
+            (void)hipEventElapsedTime(&ms[first], ev[0], ev[1]);
+            (void)hipEventElapsedTime(&ms[1 - first], ev[1], ev[2]);
+            r.push_back(ms[1] / std::max(ms[0], 1e-6f));
+        }
+        for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+        if (st != BSPL_OK) return st;
+        std::sort(r.begin(), r.end());
+        const float med = r[r.size() / 2];
+        std::vector<float> dev;
+        for (float x : r) dev.push_back(std::fabs(x - med));
+        std::sort(dev.begin(), dev.end());
+        *ratio = med;
+        *noise = 1.4826f * dev[dev.size() / 2];
+        return BSPL_OK;
+    }
+
+    void release(hipStream_t s) {
+        (void)hipStreamSynchronize(s);
+        for (int l = 0; l < 2; ++l)
+            if (t[l]) spline_table_destroy(t[l]);
+        if (mem) (void)hipFree(mem);
+        if (coefs) (void)hipFree(coefs);
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -338,43 +438,35 @@ bspl_status spline_layout_select(int nx, int ny, int nz, int64_t n_splines, bspl
     const int32_t nc[3] = {nx, ny, nz};
     const unsigned flags[2] = {0u, BSPL_LAYOUT_BLOCKED};
     const char* prefixes[2] = {"single", "single-blocked"};
-    float best[2] = {-1.f, -1.f};
-    float* zeros = nullptr;
+    LayoutRace race{};
+    // both layouts as temporary tables of the real shape, with random
+    // coefficients like a real table's
+    const size_t elems = (size_t)nx * ny * nz * (size_t)n_splines;
+    hipError_t e = hipMalloc((void**)&race.coefs, sizeof(float) * elems);
+    if (e == hipSuccess) {
+        clear_last_error();
+        hipLaunchKernelGGL(random_coefs, dim3((unsigned)((elems + 255) / 256)), dim3(256), 0, s,
+                           race.coefs, (int64_t)elems, 0xc0ef0000ull);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) st = hip_fail(e, "layout selection coefficients");
+    for (int l = 0; l < 2 && st == BSPL_OK; ++l)
+        st = spline_table_create(&race.t[l], nx, ny, nz, n_splines, race.coefs, dtype, nullptr,
+                                 BSPL_COEFS_DEVICE | flags[l], stream);
+    // each layout at its best tile: the wisdom cache, else a sweep
     for (int l = 0; l < 2 && st == BSPL_OK; ++l) {
         char key[256];
         wisdom_key(key, sizeof key, dtype, kind, n_splines, nc, npos, prefixes[l]);
-        bspl_tile tile;
         float us = -1.f;
-        if (wisdom_lookup(key, &tile, &us) && us > 0.f) {
-            best[l] = us;
-            continue;
-        }
-        // tune this layout on a temporary table of the real shape
-        const size_t elems = (size_t)nx * ny * nz * (size_t)n_splines;
-        if (!zeros) {
-            hipError_t e = hipMalloc((void**)&zeros, sizeof(float) * elems);
-            if (e == hipSuccess) e = hipMemsetAsync(zeros, 0, sizeof(float) * elems, s);
-            if (e != hipSuccess) {
-                st = hip_fail(e, "layout selection coefficients");
-                break;
-            }
-        }
-        bspl_table* t = nullptr;
-        st = spline_table_create(&t, nx, ny, nz, n_splines, zeros, dtype, nullptr,
-                                 BSPL_COEFS_DEVICE | flags[l], stream);
-        if (st != BSPL_OK) break;
-        st = spline_autotune(t, kind, npos, wisdom_path, nullptr, stream);
-        spline_table_destroy(t);
-        if (st == BSPL_OK && !(wisdom_lookup(key, &tile, &us) && us > 0.f))
-            st = fail(BSPL_EDEVICE, "layout selection found no timing for %s", key);
-        best[l] = us;
+        if (!(wisdom_lookup(key, &race.tile[l], &us) && us > 0.f))
+            st = spline_autotune(race.t[l], kind, npos, wisdom_path, &race.tile[l], stream);
     }
-    if (zeros) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(zeros);
-    }
+    float ratio = 1.f, noise = 0.f;
+    if (st == BSPL_OK) st = race.run(kind, npos, s, &ratio, &noise);
+    race.release(s);
     if (st != BSPL_OK) return st;
-    *layout = best[1] < best[0] ? BSPL_LAYOUT_BLOCKED : 0u;
+    // blocked only when it wins by more than the measured noise
+    *layout = ratio < 1.f - std::max(kLayoutMinMargin, 2.f * noise) ? BSPL_LAYOUT_BLOCKED : 0u;
     return BSPL_OK;
 }
 

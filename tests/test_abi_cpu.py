@@ -221,6 +221,19 @@ def test_null_handles():
                                      None) == B.BSPL_EINVAL
 
 
+def test_stream_probe_argument_checks():
+    """The bandwidth probe validates everything before its launch."""
+    f = B.lib.spline_stream_probe
+    assert f(None, None, 0, 1, 0, 0, None) == B.BSPL_OK        # nothing to move
+    assert f(None, None, -1, 1, 0, 0, None) == B.BSPL_EINVAL
+    assert f(None, None, 10, 1, 0, 0, None) == B.BSPL_EINVAL   # NULL buffers
+    assert f(None, None, 0, 3, 0, 0, None) == B.BSPL_EINVAL    # per_lane not 1, 2, 4
+    assert f(None, None, 0, 1, -1, 0, None) == B.BSPL_EINVAL
+    assert f(None, None, 0, 1, 0, 0x4, None) == B.BSPL_EINVAL
+    assert f(1, 1, 100, 1, 0, B.BSPL_PROBE_CHUNKED, None) == B.BSPL_EINVAL  # not 64k
+    assert f(1, 1, 1 << 62, 1, 0, 0, None) == B.BSPL_EUNSUPPORTED
+
+
 def test_batch_plan_argument_checks():
     h = ctypes.c_void_p()
     z64 = (ctypes.c_int64 * 17)()
