@@ -144,30 +144,39 @@ def timed_steps(torch, fn, nb, steps, warmup):
 def memory_ceiling(torch, B, footprints_gib=(1, 16)):
     """Best bandwidth of the streaming probe (spline_stream_probe: 6 reads of
     16 bytes per 16-byte write, the evaluation's 86/14 read/write mix) over
-    its launch variants, at each footprint (reads plus writes)."""
+    its launch variants, at each footprint (reads plus writes): reads from
+    six planes, from one 6 KiB span per wavefront in order, or from spans
+    drawn at random (the statistics of rows gathered for random positions,
+    Infinity Cache hits included)."""
     stream = torch.cuda.current_stream().cuda_stream
     out = {}
     for gib in footprints_gib:
         units = (gib << 30) // 112 // 64 * 64
         src = torch.ones(6 * units * 4, dtype=torch.int32, device="cuda")
         dst = torch.empty(units * 4, dtype=torch.int32, device="cuda")
-        best = None
-        for flags in (0, B.BSPL_PROBE_NT_STORES, B.BSPL_PROBE_CHUNKED,
-                      B.BSPL_PROBE_CHUNKED | B.BSPL_PROBE_NT_STORES):
-            for u in (1, 2, 4):
-                for grid in (0, 2048, 8192):
-                    ms = timed(torch, lambda i: B.spline_stream_probe(src, dst, units, u, grid,
-                                                                      flags, stream),
-                               20 if gib == 1 else 5, 2)
-                    gbs = 112 * units / (ms * 1e-3) / 1e9
-                    if best is None or gbs > best[0]:
-                        best = (gbs, u, grid, flags)
+        modes = {"planes": 0, "chunked": B.BSPL_PROBE_CHUNKED, "random": B.BSPL_PROBE_RANDOM}
+        row = {}
+        for mname, mflag in modes.items():
+            best = None
+            for nt in (0, B.BSPL_PROBE_NT_STORES):
+                for u in (1, 2, 4):
+                    for grid in (0, 2048, 8192):
+                        # a new salt per call: random spans differ between calls
+                        ms = timed(torch, lambda i: B.spline_stream_probe(
+                            src, dst, units, u, grid, mflag | nt, 1000 + i, stream),
+                            20 if gib == 1 else 5, 2)
+                        gbs = 112 * units / (ms * 1e-3) / 1e9
+                        if best is None or gbs > best[0]:
+                            best = (gbs, u, grid, nt)
+            row[mname] = {"gbs": best[0], "per_lane": best[1], "grid": best[2],
+                          "nt_stores": bool(best[3])}
         torch.cuda.synchronize()
         if int(dst[0].item()) != 6:
             raise RuntimeError("stream probe wrote a wrong sum")
-        out[f"mix_86_14_{gib}GiB"] = {"gbs": best[0], "per_lane": best[1], "grid": best[2],
-                                      "nt_stores": bool(best[3] & B.BSPL_PROBE_NT_STORES),
-                                      "chunked": bool(best[3] & B.BSPL_PROBE_CHUNKED)}
+        top = max(row, key=lambda k: row[k]["gbs"])
+        row["best_mode"] = top
+        row["gbs"] = row[top]["gbs"]
+        out[f"mix_86_14_{gib}GiB"] = row
         del src, dst
         torch.cuda.empty_cache()
     return out
@@ -205,14 +214,18 @@ def main(argv=None):
                     help="profiling: table dtype of the --profile run")
     ap.add_argument("--batched", action="store_true",
                     help="profiling: the four-table plan (autotuned, or --tile), 20 replays")
+    ap.add_argument("--large", action="store_true",
+                    help="profiling: eval_vgh on the 96^3 x N=4096 table (--dtype), 8192 "
+                         "positions per batch, 2 batches, autotuned or --tile, 20 launches")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args(argv)
     if args.blocked and not args.profile:
         ap.error("--blocked is for --profile runs")
 
-    if (args.npos != NPOS or args.dtype != "f32" or args.batched) and not args.profile:
-        ap.error("--npos, --dtype and --batched are for --profile runs only")
+    if (args.npos != NPOS or args.dtype != "f32" or args.batched or args.large) \
+            and not args.profile:
+        ap.error("--npos, --dtype, --batched and --large are for --profile runs only")
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the evaluation "
               "shards by replicating the table and splitting positions, with no "
@@ -235,6 +248,8 @@ def main(argv=None):
         return 0
     if args.batched:
         return batched_profile(torch, B, A, synth, args)
+    if args.large:
+        return large_profile(torch, B, A, synth, args)
 
     t0 = time.time()
     coef = synth.coef_table(*GRID, NSPL, stream=synth.table_stream(0))
@@ -563,6 +578,33 @@ CFG4 = [((32, 32, 32), 256, 97), ((40, 40, 40), 512, 512), ((48, 48, 48), 1152, 
         ((64, 64, 64), 2048, 3000)]
 
 
+def large_profile(torch, B, A, synth, args):
+    """eval_vgh on the 96^3 x N=4096 table alone (for counter and trace runs):
+    --dtype, autotuned or --tile, 5 warm-up and 20 timed launches alternating
+    two 8192-position batches."""
+    grid, n, npos = (96, 96, 96), 4096, 8192
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    src = synth.coef_table_torch(torch, *grid, n, device=dev, stream=synth.table_stream(0))
+    t = B.spline_table_create(*grid, n, src, args.dtype, flags=B.BSPL_COEFS_DEVICE)
+    del src
+    torch.cuda.empty_cache()
+    pos = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0), batch=b))
+           .to(dev) for b in range(2)]
+    v = torch.empty(npos, n, device=dev)
+    g = torch.empty(npos, 3, n, device=dev)
+    h = torch.empty(npos, 6, n, device=dev)
+    tile = (B.bspl_tile(*[int(x) for x in args.tile.split(",")]) if args.tile
+            else B.spline_autotune(t, "vgh", npos))
+    ms = timed(torch, lambda i: B.spline_eval(t, "vgh", npos, pos[i % 2], v, g, h, n, tile=tile,
+                                              stream=stream), 20, 5)
+    alg = A.batch_bytes("vgh", args.dtype, npos, n)
+    log(f"[bench] large {args.dtype} tile {tile}: {ms * 1e3:.1f} us/launch, "
+        f"{alg / (ms * 1e-3) / 1e9:.0f} GB/s")
+    B.spline_table_destroy(t)
+    return 0
+
+
 def batched_profile(torch, B, A, synth, args):
     """The four-table plan alone (for counter and trace runs): autotuned or
     --tile, 5 warm-up and 20 timed replays of one position set."""
@@ -784,6 +826,11 @@ def large_extra(torch, B, A, synth, warmup):
     src = synth.coef_table_torch(torch, *grid, n, device=dev, stream=synth.table_stream(0))
     tabs = {dt: B.spline_table_create(*grid, n, src, dt, flags=B.BSPL_COEFS_DEVICE)
             for dt in ("f32", "f16")}
+    # the interpolating fit at this size, in place on the coefficient array
+    # (three axis passes, 24 bytes per element: one read and one write each)
+    ms_fit = timed(torch, lambda i: B.spline_fit_interpolating(*grid, n, src, src, stream=stream),
+                   3, 1)
+    fit_bytes = 3 * 8 * src.numel()
     del src
     torch.cuda.empty_cache()
     nb = 2
@@ -793,7 +840,10 @@ def large_extra(torch, B, A, synth, warmup):
     g = torch.empty(npos, 3, n, device=dev)
     lh = torch.empty(npos, 6, n, device=dev)
     res = {"workload": "96^3 (99^3 padded) x N=4096 table, FP32 15.9 GB / FP16 7.9 GB, "
-                       "8192 uniform positions per batch, 2 batches alternated"}
+                       "8192 uniform positions per batch, 2 batches alternated",
+           "fit_interpolating": {"ms": ms_fit, "alg_bytes": fit_bytes,
+                                 "hbm_gbs": fit_bytes / (ms_fit * 1e-3) / 1e9,
+                                 "frac_of_peak": fit_bytes / (ms_fit * 1e-3) / 1e9 / HBM_PEAK_GBS}}
     for dt, t in tabs.items():
         for kind in ("vgh", "vgl"):
             tile = B.spline_autotune(t, kind, npos)

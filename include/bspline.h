@@ -148,8 +148,13 @@ typedef struct {
  * a 16x16x16 coarsening of the grid (a counting sort per chunk of 4096
  * positions, on the device, in stream-ordered scratch memory) so that
  * positions sharing table rows are evaluated together; order = 2 also hands
- * each of the 8 XCDs a contiguous run of the ordered blocks.  The order
- * changes no result: every output is computed the same way.  A single
+ * each of the 8 XCDs a contiguous run of the ordered blocks.  Orders 3 and
+ * 4 number the work blocks spline tiles outer instead of positions outer:
+ * every position of one spline tile is evaluated before the next tile, so
+ * the rows of a tile stay in L2 while neighbouring positions re-read them
+ * (order 3: positions in input order; order 4: cell-sorted and
+ * XCD-grouped as order 2).  The order changes no result: every output is
+ * computed the same way.  A single
  * ordered evaluation takes its permutation from hipMallocAsync on the
  * stream; for graph replay use a batch plan, which owns that memory.
  * split = 2 or 4 is the latency mode for a few positions (the GPU form of
@@ -158,15 +163,16 @@ typedef struct {
  * unit, each gathering 1/split of its 16 row groups with all of them in
  * flight, and the partial sums are added in LDS in a fixed order.  A split
  * workgroup holds wx tiles x split wavefronts of one position (wy must be
- * 1, grid 0, wx*split <= 8, and split*wx*n_out*vw*256 bytes of partial sums
- * at most 64 KiB).  Results differ from split = 1 only by rounding; split
+ * 1, grid 0, order at most 2, wx*split <= 8, and split*wx*n_out*vw*256
+ * bytes of partial sums at most 64 KiB).  Results differ from split = 1 only by rounding; split
  * = 0 means 1.  Evaluations only (not ratios or batch plans).            */
 typedef struct {
     int32_t vw;    /* splines per lane: 1, 2, 4 (F32) or 2, 4, 8 (F16/BF16) */
     int32_t wx;    /* wavefronts per workgroup along splines */
     int32_t wy;    /* wavefronts per workgroup along positions */
     int32_t grid;  /* persistent workgroups, or 0 */
-    int32_t order; /* 0 input order, 1 cell-sorted, 2 cell-sorted + XCD-grouped */
+    int32_t order; /* 0 input order, 1 cell-sorted, 2 cell-sorted + XCD-grouped,
+                      3 input order tile-major, 4 as 2 tile-major */
     int32_t split; /* 0 or 1; 2 or 4 wavefronts per unit (latency mode) */
 } bspl_tile;
 
@@ -285,7 +291,7 @@ bspl_status spline_launch_query(const bspl_table_info* layout, bspl_kind kind, i
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, checks, kernels and results as
  * spline_eval, with two differences:
- *  - a cell-ordered tile (order 1 or 2) keeps its permutation in a static
+ *  - a cell-sorted tile (order 1, 2 or 4) keeps its permutation in a static
  *    device array of BSPL_NOALLOC_MAX_POSITIONS int32 entries (4 MiB, held
  *    by each device the library runs on until the process ends) instead of
  *    stream-ordered scratch memory; npos beyond that limit with an ordered

@@ -35,6 +35,7 @@ MAX_TABLES = 16
 NOALLOC_MAX_POSITIONS = 1 << 20
 BSPL_PROBE_NT_STORES = 0x1
 BSPL_PROBE_CHUNKED = 0x2
+BSPL_PROBE_RANDOM = 0x4
 
 DTYPES = {"f32": BSPL_F32, "f16": BSPL_F16, "bf16": BSPL_BF16}
 KINDS = {"v": BSPL_V, "vgl": BSPL_VGL, "vgh": BSPL_VGH}
@@ -111,7 +112,7 @@ _SIGS = {
     "spline_batch_plan_tile": (_int, [_vp, _P(bspl_tile)]),
     "spline_batch_plan_destroy": (_int, [_vp]),
     "spline_stream_probe": (_int, [_vp, _vp, _i64, ctypes.c_int32, ctypes.c_int32,
-                                   ctypes.c_int32, _vp]),
+                                   ctypes.c_int32, ctypes.c_uint64, _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(lib, _name)
@@ -348,8 +349,9 @@ def spline_batch_plan_destroy(plan) -> None:
     _check(lib.spline_batch_plan_destroy(plan), "spline_batch_plan_destroy")
 
 
-def spline_stream_probe(src, dst, units, per_lane=1, grid=0, flags=0, stream=None) -> None:
+def spline_stream_probe(src, dst, units, per_lane=1, grid=0, flags=0, salt=0,
+                        stream=None) -> None:
     """Measurement helper (bspline_probe.h): 6 reads of 16 bytes per 16-byte
     write; src holds 6 * units words, dst units words."""
-    _check(lib.spline_stream_probe(_ptr(src), _ptr(dst), units, per_lane, grid, flags,
+    _check(lib.spline_stream_probe(_ptr(src), _ptr(dst), units, per_lane, grid, flags, salt,
                                    _stream(stream)), "spline_stream_probe")

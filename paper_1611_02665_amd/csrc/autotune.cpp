@@ -152,7 +152,7 @@ std::vector<bspl_tile> tile_candidates(int dtype, int kind, int64_t max_nsplines
             const int* grids = persistent ? grids_p : grids_s;
             const int ng = persistent ? 5 : 1;
             for (int gi = 0; gi < ng; ++gi)
-                for (int order = 0; order <= 2; ++order)
+                for (int order = 0; order <= kMaxOrder; ++order)
                     out.push_back(bspl_tile{vw, s[0], s[1], grids[gi] * cus, order, 1});
         }
         // latency mode (single evaluations): wx tiles x split wavefronts per

@@ -28,9 +28,9 @@ struct bspl_plan {
     int64_t npos[bspl::kMaxTables] = {};
     int64_t ldo[bspl::kMaxTables] = {};
     bspl::KernelArgs<bspl::kMaxTables> args{};
-    int32_t* d_perm = nullptr;               // cell orders of all tables (order > 0)
+    int32_t* d_perm = nullptr;               // cell orders of all tables (sorted orders)
     int64_t perm_off[bspl::kMaxTables] = {};
-    bspl::OrderTables otab{};                // the ordering launch's argument (order > 0)
+    bspl::OrderTables otab{};                // the ordering launch's argument (sorted orders)
     void* oargs[1] = {};
     hipGraphNode_t order_node = nullptr;
     hipGraph_t graph = nullptr;
@@ -65,7 +65,7 @@ bspl_status build_args(const bspl_plan& p, const bspl_tile& tile, const Bindings
                                    tile.vw, tile.wx, tile.wy, &d);
         if (st != BSPL_OK) return st;
         d.groups_begin = begin;
-        if (tile.order > 0 && perm_base) d.perm = perm_base + p.perm_off[i];
+        if (order_sorted(tile.order) && perm_base) d.perm = perm_base + p.perm_off[i];
         begin += (int64_t)d.xgroups * ((p.npos[i] + tile.wy - 1) / tile.wy);
         a.t[i] = d;
     }
@@ -74,7 +74,8 @@ bspl_status build_args(const bspl_plan& p, const bspl_tile& tile, const Bindings
     a.ntables = p.ntables;
     a.wx = tile.wx;
     a.wy = tile.wy;
-    a.xcd_remap = tile.order == 2 ? 1 : 0;
+    a.xcd_remap = order_xcd(tile.order) ? 1 : 0;
+    a.tile_major = order_tile_major(tile.order) ? 1 : 0;
     *out = a;
     return BSPL_OK;
 }
@@ -131,7 +132,7 @@ bspl_status run_batch(void* vctx, const bspl_tile& tile, int it) {
     KernelArgs<kMaxTables> a;
     bspl_status st = build_args(*c->p, tile, c->b[it & 1], &a, c->perm);
     if (st != BSPL_OK) return st;
-    if (tile.order > 0) {
+    if (order_sorted(tile.order)) {
         OrderTables o;
         order_tables_config(a, &o);
         st = launch_order_tables(o, c->s);
@@ -206,13 +207,13 @@ bool order_params(bspl_plan* p, hipKernelNodeParams* kp) {
     return chunks > 0;
 }
 
-// Graph: [one ordering node for all tables (order > 0)] -> one evaluation node.
+// Graph: [one ordering node for all tables (sorted orders)] -> one evaluation node.
 bspl_status instantiate(bspl_plan* p) {
     const void* fn = multi_kernel_ptr(p->dtype, p->kind, p->tile.vw, plan_lattice(*p));
     if (!fn) return fail(BSPL_EINVAL, "no batched kernel for vw=%d", p->tile.vw);
     BSPL_HIP(hipGraphCreate(&p->graph, 0));
     std::vector<hipGraphNode_t> deps;
-    if (p->tile.order > 0) {
+    if (order_sorted(p->tile.order)) {
         hipKernelNodeParams op;
         if (order_params(p, &op)) {
             BSPL_HIP(hipGraphAddKernelNode(&p->order_node, p->graph, nullptr, 0, &op));
@@ -372,7 +373,7 @@ bspl_status spline_batch_launch(bspl_plan* p, void* stream) {
     if (!p) return fail(BSPL_EINVAL, "plan is NULL");
     if (p->args.total_groups == 0) return BSPL_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (p->tile.order > 0) {
+    if (order_sorted(p->tile.order)) {
         hipKernelNodeParams op;
         if (order_params(p, &op))
             BSPL_HIP(hipLaunchKernel(op.func, op.gridDim, op.blockDim, op.kernelParams,

@@ -499,7 +499,8 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t total) {
 
 // One launch over one or several tables.  Workgroup-block g covers wx
 // spline tiles by wy positions of one table; blocks are numbered table by
-// table, positions outer, tiles inner.  With fewer workgroups than blocks
+// table, positions outer and tiles inner, or tiles outer and positions inner
+// (tile_major).  With fewer workgroups than blocks
 // (persistent launch) each workgroup strides over the blocks.
 template <typename T, int VW, int KIND, int MAXT, int LAT>
 __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
@@ -516,8 +517,15 @@ __global__ void __launch_bounds__(512) eval_kernel(const KernelArgs<MAXT> a) {
         }
         const TableDesc& d = a.t[ti];
         const int local = (int)(g - d.groups_begin);
-        const int pg = local / d.xgroups;
-        const int cg = local - pg * d.xgroups;
+        int pg, cg;
+        if (a.tile_major) {  // tiles outer: every position of a tile, then the next tile
+            const int ygroups = (int)((d.npos + a.wy - 1) / a.wy);
+            cg = local / ygroups;
+            pg = local - cg * ygroups;
+        } else {             // positions outer
+            pg = local / d.xgroups;
+            cg = local - pg * d.xgroups;
+        }
         const int chunk = cg * a.wx + wxi;
         const int q = pg * a.wy + wyi;
         if (chunk < d.nchunks && q < d.npos) {

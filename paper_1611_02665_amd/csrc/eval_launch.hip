@@ -89,7 +89,8 @@ bspl_status launch_single(const bspl_table* t, int kind, const TableDesc& d,
     a.ntables = 1;
     a.wx = tile.wx;
     a.wy = tile.wy;
-    a.xcd_remap = tile.order == 2 ? 1 : 0;
+    a.xcd_remap = order_xcd(tile.order) ? 1 : 0;
+    a.tile_major = order_tile_major(tile.order) ? 1 : 0;
     const int64_t ygroups = (d.npos + tile.wy - 1) / tile.wy;
     a.total_groups = ygroups * d.xgroups;
     return launch<1>(kernel_for(t->info.dtype, kind, tile.vw, 0, d.lattice), a, tile, s);

@@ -30,6 +30,18 @@ constexpr int kXcds = 8;
 // tile lies in one block.
 inline int64_t block_splines_of(int dtype) { return dtype == BSPL_F32 ? 256 : 512; }
 
+// Evaluation orders (bspl_tile.order): 0 input order; 1 cell-sorted; 2
+// cell-sorted with each XCD taking a contiguous run of blocks; 3 input order,
+// spline-tile-major; 4 as 2, spline-tile-major.  Position-major numbers the
+// work blocks positions outer, spline tiles inner (a position's tiles run
+// side by side); spline-tile-major numbers them tiles outer, so that all
+// positions of one spline tile run before the next tile and a tile's rows
+// stay in L2 while its positions are evaluated.
+constexpr int kMaxOrder = 4;
+inline bool order_sorted(int order) { return order == 1 || order == 2 || order == 4; }
+inline bool order_xcd(int order) { return order == 2 || order == 4; }
+inline bool order_tile_major(int order) { return order == 3 || order == 4; }
+
 // Record a failure message for spline_last_error() and return the status.
 bspl_status fail(bspl_status s, const char* fmt, ...);
 bspl_status hip_fail(hipError_t e, const char* what);
@@ -78,6 +90,7 @@ struct KernelArgs {
     int32_t wx;
     int32_t wy;
     int32_t xcd_remap;        // give each XCD a contiguous run of blocks
+    int32_t tile_major;       // blocks numbered spline tiles outer, positions inner
 };
 
 // Fill a descriptor for table t (positions and outputs included).

@@ -69,13 +69,13 @@ extern "C" bspl_status spline_eval_noalloc(const bspl_table* t, bspl_kind kind, 
         }
     }
     // the scratch limit is a host check, made before any HIP call
-    if (tl.order > 0 && npos > kNoAllocMaxPositions)
+    if (order_sorted(tl.order) && npos > kNoAllocMaxPositions)
         return fail(BSPL_EUNSUPPORTED,
                     "a cell-ordered evaluation of %lld positions needs more than the %lld "
                     "positions of static scratch memory", (long long)npos,
                     (long long)kNoAllocMaxPositions);
     int32_t* perm = nullptr;
-    if (tl.order > 0 && npos > 0) {
+    if (order_sorted(tl.order) && npos > 0) {
         const bspl_status st = scratch_address(&perm);
         if (st != BSPL_OK) return st;
     }

@@ -42,10 +42,11 @@ bool tile_valid(const bspl_tile& tile, int dtype) {
     const bool vw_ok = f32 ? (tile.vw == 1 || tile.vw == 2 || tile.vw == 4)
                            : (tile.vw == 2 || tile.vw == 4 || tile.vw == 8);
     const bool base_ok = vw_ok && tile.wx >= 1 && tile.wy >= 1 && tile.wx * tile.wy <= 8 &&
-                         tile.grid >= 0 && tile.order >= 0 && tile.order <= 2;
+                         tile.grid >= 0 && tile.order >= 0 && tile.order <= kMaxOrder;
     if (tile.split == 0 || tile.split == 1) return base_ok;
+    // a split unit is one workgroup per position: the block order is fixed
     return base_ok && (tile.split == 2 || tile.split == 4) && tile.wy == 1 && tile.grid == 0 &&
-           tile.wx * tile.split <= 8;
+           tile.wx * tile.split <= 8 && tile.order <= 2;
 }
 
 // The decomposition used without a tuned one, from the measurements on
@@ -518,7 +519,7 @@ bspl_status eval_checked(const bspl_table* t, int kind, int64_t npos, const doub
     LaunchShape ls;
     bspl_status st = launch_shape(t->info, npos, tl, &ls);
     if (st != BSPL_OK) return st;
-    if (tl.order > 0 && perm && npos > perm_capacity)
+    if (order_sorted(tl.order) && perm && npos > perm_capacity)
         return fail(BSPL_EUNSUPPORTED,
                     "a cell-ordered evaluation of %lld positions needs more than the %lld "
                     "positions of static scratch memory", (long long)npos,
@@ -527,7 +528,7 @@ bspl_status eval_checked(const bspl_table* t, int kind, int64_t npos, const doub
     st = make_desc(t, npos, pos, v, kind == BSPL_V ? nullptr : g, kind == BSPL_V ? nullptr : lh,
                    ldo, tl.vw, tl.wx, tl.wy, &d);
     if (st != BSPL_OK) return st;
-    if (tl.order == 0) return launch_single(t, kind, d, tl, s);
+    if (!order_sorted(tl.order)) return launch_single(t, kind, d, tl, s);
     if (perm) {  // the caller's scratch: the permutation is fully rewritten
         st = launch_order(d, perm, s);
         if (st != BSPL_OK) return st;

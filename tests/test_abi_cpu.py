@@ -224,15 +224,15 @@ def test_null_handles():
 def test_stream_probe_argument_checks():
     """The bandwidth probe validates everything before its launch."""
     f = B.lib.spline_stream_probe
-    assert f(None, None, 0, 1, 0, 0, None) == B.BSPL_OK        # nothing to move
-    assert f(None, None, -1, 1, 0, 0, None) == B.BSPL_EINVAL
-    assert f(None, None, 10, 1, 0, 0, None) == B.BSPL_EINVAL   # NULL buffers
-    assert f(None, None, 0, 3, 0, 0, None) == B.BSPL_EINVAL    # per_lane not 1, 2, 4
-    assert f(None, None, 0, 1, -1, 0, None) == B.BSPL_EINVAL
-    assert f(None, None, 0, 1, 0, 0x4, None) == B.BSPL_EINVAL
-    assert f(1, 1, 100, 1, 0, B.BSPL_PROBE_CHUNKED, None) == B.BSPL_EINVAL  # not 64k
-    assert f(1, 1, 1 << 62, 1, 0, 0, None) == B.BSPL_EUNSUPPORTED
-
+    assert f(None, None, 0, 1, 0, 0, 0, None) == B.BSPL_OK        # nothing to move
+    assert f(None, None, -1, 1, 0, 0, 0, None) == B.BSPL_EINVAL
+    assert f(None, None, 10, 1, 0, 0, 0, None) == B.BSPL_EINVAL   # NULL buffers
+    assert f(None, None, 0, 3, 0, 0, 0, None) == B.BSPL_EINVAL    # per_lane not 1, 2, 4
+    assert f(None, None, 0, 1, -1, 0, 0, None) == B.BSPL_EINVAL
+    assert f(None, None, 0, 1, 0, 0x8, 0, None) == B.BSPL_EINVAL
+    for fl in (B.BSPL_PROBE_CHUNKED, B.BSPL_PROBE_RANDOM):
+        assert f(1, 1, 100, 1, 0, fl, 0, None) == B.BSPL_EINVAL   # not a multiple of 64
+    assert f(1, 1, 1 << 62, 1, 0, 0, 0, None) == B.BSPL_EUNSUPPORTED
 
 def test_batch_plan_argument_checks():
     h = ctypes.c_void_p()
@@ -322,7 +322,13 @@ def test_launch_query_limits_without_a_device():
     assert q == {"units": 3 * 100, "workgroups": 300, "threads": 256}
     # npos = 0: nothing to launch
     assert B.spline_launch_query(lay, "v", 0, (1, 1, 1, 0, 0, 1))["workgroups"] == 0
-    for bad in ((3, 1, 1, 0, 0, 1), (1, 1, 1, 0, 3, 1), (1, 4, 1, 0, 0, 4)):
+    # orders 3 and 4 (spline-tile-major) are valid tiles; order 5 is not, and
+    # split units keep orders 0..2
+    for order in (3, 4):
+        q = B.spline_launch_query(lay, "vgh", 10, (1, 1, 1, 0, order, 1))
+        assert q["units"] == 11 * 10
+    for bad in ((3, 1, 1, 0, 0, 1), (1, 1, 1, 0, 5, 1), (1, 4, 1, 0, 0, 4),
+                (1, 1, 1, 0, 3, 4), (1, 1, 1, 0, -1, 1)):
         with pytest.raises(B.BsplineError) as e:
             B.spline_launch_query(lay, "vgh", 10, bad)
         assert e.value.status == B.BSPL_EINVAL, bad

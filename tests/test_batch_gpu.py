@@ -58,7 +58,8 @@ SMALL_NPOS = [7, 50, 130, 300]
 
 
 @pytest.mark.parametrize("kind", ["v", "vgl", "vgh"])
-@pytest.mark.parametrize("tile", [(2, 2, 1, 64, 0), (4, 1, 2, 256, 1), (1, 4, 1, 1000, 2)])
+@pytest.mark.parametrize("tile", [(2, 2, 1, 64, 0), (4, 1, 2, 256, 1), (1, 4, 1, 1000, 2),
+                                  (2, 1, 2, 0, 3), (1, 2, 2, 0, 4), (2, 2, 1, 128, 4)])
 def test_batch_plan_replays(kind, tile):
     T = Tables(SMALL)
     dev = torch.device("cuda")
@@ -219,7 +220,8 @@ def test_config4_batched_sampled(dtype, bound):
             B.spline_table_destroy(h)
 
 
-@pytest.mark.parametrize("tile", [(1, 2, 1, 0, 0, 1), (2, 4, 1, 0, 1, 1), (4, 1, 2, 64, 2, 1)])
+@pytest.mark.parametrize("tile", [(1, 2, 1, 0, 0, 1), (2, 4, 1, 0, 1, 1), (4, 1, 2, 64, 2, 1),
+                                  (1, 2, 2, 0, 4, 1)])
 def test_batch_launch_matches_execute(tile):
     """spline_batch_launch issues the plan's kernels without the graph: the
     same bits as a graph replay, before and after a rebind, and inside a

@@ -108,7 +108,7 @@ def test_lattice_order_changes_no_result(dtype):
     pos = cell_positions(9000, HEX, stream=86, lo=-0.5, hi=1.5)
     with LatticeTable(coef, HEX, dtype) as t:
         outs = []
-        for order in (0, 1, 2):
+        for order in (0, 1, 2, 3, 4):
             _, raw = run_gpu(B, t.h, "vgh", pos, 260, tile=(2, 2, 2, 0, order))
             outs.append(raw)
         for o in outs[1:]:

@@ -134,7 +134,7 @@ def test_all_tiles_ragged(ragged, dtype):
 def test_invalid_tiles_rejected(cfg1):
     _, pos, t = cfg1
     for tile in [(3, 1, 1, 0, 0), (8, 1, 1, 0, 0), (4, 0, 1, 0, 0), (4, 4, 4, 0, 0),
-                 (4, 1, 1, -1, 0), (4, 1, 1, 0, 3), (4, 1, 1, 0, -1),
+                 (4, 1, 1, -1, 0), (4, 1, 1, 0, 5), (4, 1, 1, 0, -1), (1, 1, 1, 0, 3, 2),
                  (1, 1, 2, 0, 0, 2), (1, 1, 1, 5, 0, 2), (1, 8, 1, 0, 0, 2), (1, 4, 1, 0, 0, 4),
                  (1, 1, 1, 0, 0, 3), (1, 1, 1, 0, 0, -1)]:
         with pytest.raises(B.BsplineError) as e:
@@ -144,13 +144,14 @@ def test_invalid_tiles_rejected(cfg1):
 
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
 def test_order_changes_no_result(dtype):
-    """Cell-sorted and XCD-grouped evaluation orders give bit-identical
-    outputs (every output is computed by the same arithmetic)."""
+    """Cell-sorted, XCD-grouped and spline-tile-major evaluation orders give
+    bit-identical outputs (every output is computed by the same arithmetic),
+    with full and persistent grids."""
     coef = synth.coef_table(20, 24, 16, 520, stream=13)
     pos = synth.positions(9000, stream=14) * 2 - 0.5  # more than one ordering chunk
     with Table(coef, dtype) as t:
         outs = []
-        for order in (0, 1, 2):
+        for order in (0, 1, 2, 3, 4):
             for grid in (0, 96):
                 o, raw = run_gpu(B, t.h, "vgh", pos, 520, ldo=520, tile=(2, 2, 2, grid, order))
                 outs.append(raw)

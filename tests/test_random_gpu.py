@@ -41,7 +41,7 @@ def _random_case(rng):
     else:
         wx = int(rng.choice([1, 2, 4, 8]))
         wy = int(rng.choice([w for w in (1, 2, 4, 8) if w * wx <= 8]))
-        tile = (vw, wx, wy, int(rng.choice([0, 0, 7, 64])), int(rng.integers(0, 3)), 1)
+        tile = (vw, wx, wy, int(rng.choice([0, 0, 7, 64])), int(rng.integers(0, 5)), 1)
     npos = int(rng.integers(1, 300))
     return dims, n, dtype, kind, cell, tile, npos
 
@@ -90,7 +90,7 @@ def test_random_plan(case):
     vw = int(rng.choice([1, 2, 4] if dtype == "f32" else [2, 4, 8]))
     wx = int(rng.choice([1, 2, 4]))
     wy = int(rng.choice([w for w in (1, 2) if w * wx <= 8]))
-    tile = (vw, wx, wy, int(rng.choice([0, 64, 256])), int(rng.integers(0, 3)), 1)
+    tile = (vw, wx, wy, int(rng.choice([0, 64, 256])), int(rng.integers(0, 5)), 1)
     dev = torch.device("cuda")
     lay = np.random.default_rng(8000 + case)  # table layouts, apart from the cases' draws
     tabs, coefs, cells, poss, outs, npos, ldos = [], [], [], [], [], [], []
