@@ -216,9 +216,11 @@ bspl_status fill_random_positions(double* pos, int64_t npos, const double box[3]
 }
 
 // Sweep tiles for a launch described by `run(tile, iteration)`: every
-// candidate timed briefly (median of 5), then the fastest few again with
-// more runs (median of 25), so that noise does not decide between tiles
-// a few percent apart.
+// candidate timed briefly (median of 5), then the fastest few again, side
+// by side: 25 rounds in which each finalist runs once, the order rotating
+// from round to round, and the median of its 25 times decides.  Timing the
+// finalists interleaved keeps clock and cache drift over the sweep from
+// deciding between tiles a few percent apart.
 bspl_status sweep(const std::vector<bspl_tile>& cands, hipStream_t s,
                   bspl_status (*run)(void*, const bspl_tile&, int), void* ctx, bspl_tile* best,
                   float* best_us) {
@@ -232,15 +234,33 @@ bspl_status sweep(const std::vector<bspl_tile>& cands, hipStream_t s,
         first.emplace_back(us, i);
     }
     std::sort(first.begin(), first.end());
-    const size_t finalists = std::min<size_t>(4, first.size());
-    for (size_t f = 0; f < finalists; ++f) {
-        const bspl_tile& t = cands[first[f].second];
-        float us = 0;
-        auto call = [&](int it) { return run(ctx, t, it); };
-        bspl_status st = time_launch(call, s, 25, &us);
-        if (st != BSPL_OK) return st;
+    const size_t nf = std::min<size_t>(4, first.size());
+    hipEvent_t a, b;
+    BSPL_HIP(hipEventCreate(&a));
+    BSPL_HIP(hipEventCreate(&b));
+    std::vector<std::vector<float>> t(nf);
+    bspl_status st = BSPL_OK;
+    for (int r = 0; r < 25 && st == BSPL_OK; ++r) {
+        for (size_t k = 0; k < nf && st == BSPL_OK; ++k) {
+            const size_t f = (k + (size_t)r) % nf;
+            (void)hipEventRecord(a, s);
+            st = run(ctx, cands[first[f].second], r);
+            (void)hipEventRecord(b, s);
+            const hipError_t e = hipEventSynchronize(b);
+            if (st == BSPL_OK && e != hipSuccess) st = hip_fail(e, "autotune timing");
+            float ms = 0;
+            if (st == BSPL_OK) (void)hipEventElapsedTime(&ms, a, b);
+            t[f].push_back(ms * 1000.f);
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != BSPL_OK) return st;
+    for (size_t f = 0; f < nf; ++f) {
+        std::sort(t[f].begin(), t[f].end());
+        const float us = t[f][t[f].size() / 2];
         if (f == 0 || us < *best_us) {
-            *best = t;
+            *best = cands[first[f].second];
             *best_us = us;
         }
     }
