@@ -397,16 +397,21 @@ def main(argv=None):
         extra["layout"] = layout_extra(torch, B, synth, coef, t32, steps, warmup)
         log("[bench] layout extra done")
         # the FP16 table on the headline's own 512-position batches
+        # (the two dtypes timed interleaved: 25 reps of 16 launches, medians)
         t16 = B.spline_table_create(*GRID, NSPL, coef, "f16")
         tile16 = B.spline_autotune(t16, "vgh", NPOS)
-        ms16 = timed(torch, lambda i: B.spline_eval(t16, "vgh", NPOS, pp[i % nbatch], v, g, h,
-                                                    ldo, tile=tile16, stream=stream),
-                     max(100, steps // 2), warmup)
+        pair = interleaved(torch, [
+            lambda i: B.spline_eval(t32, "vgh", NPOS, pp[i % nbatch], v, g, h, ldo, tile=tile,
+                                    stream=stream),
+            lambda i: B.spline_eval(t16, "vgh", NPOS, pp[i % nbatch], v, g, h, ldo, tile=tile16,
+                                    stream=stream)], nbatch, reps=25)
+        ms32i, ms16 = median(pair[0]), median(pair[1])
         B.spline_table_destroy(t16)
         extra["f16_headline_batches"] = {
             "evals_per_s": evals / (ms16 * 1e-3), "us_per_launch": ms16 * 1e3,
             "hbm_gbs": A.batch_bytes("vgh", "f16", NPOS, NSPL) / (ms16 * 1e-3) / 1e9,
-            "tile": list(tile16.as_tuple()), "speedup_vs_f32_headline": ms / ms16}
+            "tile": list(tile16.as_tuple()), "f32_us_per_launch_interleaved": ms32i * 1e3,
+            "speedup_vs_f32_headline": ms32i / ms16}
         # interpolating coefficients from grid values (table set-up, once per
         # orbital set): one HBM read and one write per element and axis
         vals = torch.from_numpy(coef).to(dev)
@@ -471,41 +476,66 @@ def main(argv=None):
 def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
     """FP16 and BF16 tables vs FP32 on the same 4096-position batches.
 
-    Errors here are against the FP32-table GPU outputs on 64 positions (the
-    FP32 table itself matches the FP64 oracle to ~3e-7; the errors against
-    the oracle are checked and printed by the GPU tests)."""
+    Each dtype runs at its own autotuned tile (and, as context, its best
+    input-order tile and the batch-plan forms).  The three dtypes of one
+    form are timed back to back (interleaved(): 15 repetitions of 4
+    launches each, rotating which goes first, medians), so that clock and
+    cache drift between separate timing loops cannot decide the ratios.
+    The deviation from the FP32-table outputs on 64 positions is context;
+    the errors against the FP64 oracle are in cpu_baseline.error_vs_oracle."""
     npos = 4096
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
     nb = 4
     batches = [torch.from_numpy(synth.positions(npos, stream=synth.position_stream(0),
                                                 batch=100 + b)).to(dev) for b in range(nb)]
-    pp = [b.data_ptr() for b in batches]
     v = torch.empty(npos, NSPL, device=dev)
     g = torch.empty(npos, 3, NSPL, device=dev)
     h = torch.empty(npos, 6, NSPL, device=dev)
-    out = {}
+    dts = ("f32", "f16", "bf16")
+    tabs = {dt: (t32 if dt == "f32" else B.spline_table_create(*GRID, NSPL, coef, dt))
+            for dt in dts}
+    tiles = {dt: B.spline_autotune(tabs[dt], "vgh", npos) for dt in dts}
+    in_tiles = {dt: best_input_order(torch, B, tabs[dt], dt, npos, batches, nb, v, g, h, stream)
+                for dt in dts}
+
+    def eval_fn(dt, tile):
+        t = tabs[dt]
+        return lambda i: B.spline_eval(t, "vgh", npos, batches[i % nb], v, g, h, NSPL,
+                                       tile=tile, stream=stream)
+
+    ms = dict(zip(dts, map(median, interleaved(torch, [eval_fn(d, tiles[d]) for d in dts],
+                                               4, reps=15))))
+    ms_in = dict(zip(dts, map(median, interleaved(
+        torch, [eval_fn(d, in_tiles[d]) for d in dts], 4, reps=15))))
+    # the batched form: the same work as one launch replayed from a HIP graph,
+    # with the plan's own autotuned tile, and with the best input-order tile
+    plans, plans_in = {}, {}
+    for dt in dts:
+        plans[dt] = [B.spline_batch_plan_create([tabs[dt]], [npos], "vgh", [b], [v], [g], [h],
+                                                [NSPL], stream=stream) for b in batches]
+        plans_in[dt] = [B.spline_batch_plan_create([tabs[dt]], [npos], "vgh", [b], [v], [g], [h],
+                                                   [NSPL], tile=tuple(in_tiles[dt][:3]) + (0, 0, 1),
+                                                   stream=stream) for b in batches]
+
+    def plan_fn(pl):
+        return lambda i: B.spline_batch_execute(pl[i % len(pl)], stream)
+
+    ms_b = dict(zip(dts, map(median, interleaved(torch, [plan_fn(plans[d]) for d in dts],
+                                                 4, reps=15))))
+    ms_bi = dict(zip(dts, map(median, interleaved(torch, [plan_fn(plans_in[d]) for d in dts],
+                                                  4, reps=15))))
+    ptiles = {dt: B.spline_batch_plan_tile(plans[dt][0]) for dt in dts}
+    for dt in dts:
+        for pl in plans[dt] + plans_in[dt]:
+            B.spline_batch_plan_destroy(pl)
+    # deviation on 64 positions from the FP32-table outputs (context)
     sample = synth.positions(64, stream=synth.position_stream(0), batch=100)
     sample_d = torch.from_numpy(sample).to(dev)  # [3][64]: npos is also the row stride
-    ref = None
-    k = max(50, steps // 8)
-    for dt in ("f32", "f16", "bf16"):
-        t = t32 if dt == "f32" else B.spline_table_create(*GRID, NSPL, coef, dt)
-        tile = B.spline_autotune(t, "vgh", npos)
-        ms = timed(torch, lambda i: B.spline_eval_vgh(t, npos, pp[i % nb], v.data_ptr(),
-                                                      g.data_ptr(), h.data_ptr(), NSPL, stream),
-                   k, warmup)
-        # input (random) order only: the paper's access pattern, no row reuse
-        in_tile, ms_in = best_input_order(torch, B, t, dt, npos, pp, nb, v, g, h, stream, warmup)
-        # the batched form: the same work as one launch replayed
-        # from a HIP graph (the plan's tile comes from its own autotuning),
-        # and the same with the best input-order tile
-        ms_b, ptile = plan_time(torch, B, t, npos, batches, v, g, h, None, stream, k, warmup)
-        ms_bi, _ = plan_time(torch, B, t, npos, batches, v, g, h,
-                             tuple(in_tile[:3]) + (0, 0, 1), stream, k, warmup)
-        # error on 64 positions against the FP32-table outputs
-        B.spline_eval_vgh(t, 64, sample_d.data_ptr(), v.data_ptr(), g.data_ptr(), h.data_ptr(),
-                          NSPL, stream)
+    out, ref = {}, None
+    for dt in dts:
+        B.spline_eval_vgh(tabs[dt], 64, sample_d.data_ptr(), v.data_ptr(), g.data_ptr(),
+                          h.data_ptr(), NSPL, stream)
         torch.cuda.synchronize()
         got = {"v": v[:64].cpu().numpy().astype(np.float64),
                "g": g[:64].cpu().numpy().astype(np.float64),
@@ -522,19 +552,20 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
                     key = name + ("xyz"[c] if name == "g" else
                                   ["xx", "xy", "xz", "yy", "yz", "zz"][c])
                     errs[key] = float(np.abs(a[:, c] - r[:, c]).max() / np.abs(r[:, c]).max())
-        out[dt] = {"evals_per_s": npos * NSPL / (ms * 1e-3), "us_per_launch": ms * 1e3,
-                   "hbm_gbs": A.batch_bytes("vgh", dt, npos, NSPL) / (ms * 1e-3) / 1e9,
-                   "tile": list(tile.as_tuple()),
-                   "input_order_evals_per_s": npos * NSPL / (ms_in * 1e-3),
-                   "input_order_us_per_launch": ms_in * 1e3, "input_order_tile": list(in_tile),
-                   "batched_evals_per_s": npos * NSPL / (ms_b * 1e-3),
-                   "batched_us_per_launch": ms_b * 1e3, "batched_tile": list(ptile.as_tuple()),
-                   "batched_input_order_evals_per_s": npos * NSPL / (ms_bi * 1e-3),
+        out[dt] = {"evals_per_s": npos * NSPL / (ms[dt] * 1e-3), "us_per_launch": ms[dt] * 1e3,
+                   "hbm_gbs": A.batch_bytes("vgh", dt, npos, NSPL) / (ms[dt] * 1e-3) / 1e9,
+                   "tile": list(tiles[dt].as_tuple()),
+                   "input_order_evals_per_s": npos * NSPL / (ms_in[dt] * 1e-3),
+                   "input_order_us_per_launch": ms_in[dt] * 1e3,
+                   "input_order_tile": list(in_tiles[dt]),
+                   "batched_evals_per_s": npos * NSPL / (ms_b[dt] * 1e-3),
+                   "batched_us_per_launch": ms_b[dt] * 1e3,
+                   "batched_tile": list(ptiles[dt].as_tuple()),
+                   "batched_input_order_evals_per_s": npos * NSPL / (ms_bi[dt] * 1e-3),
                    "max_norm_err_vs_f32_table": max(errs.values()),
                    "err_vs_f32_table_per_component": errs}
-        if dt != "f32":
-            B.spline_table_destroy(t)
     for dt in ("f16", "bf16"):
+        B.spline_table_destroy(tabs[dt])
         for key in ("evals_per_s", "input_order_evals_per_s", "batched_evals_per_s",
                     "batched_input_order_evals_per_s"):
             name = key.replace("evals_per_s", "speedup_vs_f32")
@@ -542,36 +573,24 @@ def precision_extra(torch, np, B, A, synth, coef, t32, steps, warmup):
     out["npos"] = npos
     out["workload"] = ("eval_vgh on the same 48^3 x N=2048 coefficients stored as FP32, FP16 "
                        "and BF16 (per-spline FP32 scales), 4096 uniform positions per batch, "
-                       "4 batches cycled; errors on 64 positions against the FP32-table "
-                       "outputs, normalised per component by max|reference|")
+                       "4 batches cycled; the dtypes of each form timed interleaved (15 reps "
+                       "of 4 launches, medians); deviation on 64 positions from the "
+                       "FP32-table outputs, normalised per component by max|reference|")
     return out
 
 
-def best_input_order(torch, B, t, dt, npos, pp, nb, v, g, h, stream, warmup):
+def best_input_order(torch, B, t, dt, npos, batches, nb, v, g, h, stream):
     """Fastest input-order (order = 0) tile from a small sweep."""
     vws = (1, 2, 4) if dt == "f32" else (2, 4, 8)
     best = None
     for vw in vws:
         for wx, wy in ((4, 1), (2, 1), (2, 2), (1, 4)):
             tile = (vw, wx, wy, 0, 0)
-            ms = timed(torch, lambda i: B.spline_eval(t, "vgh", npos, pp[i % nb], v, g, h, NSPL,
-                                                      tile=tile, stream=stream), 20, 3)
+            ms = timed(torch, lambda i: B.spline_eval(t, "vgh", npos, batches[i % nb], v, g, h,
+                                                      NSPL, tile=tile, stream=stream), 20, 3)
             if best is None or ms < best[1]:
                 best = (tile, ms)
-    tile = best[0]
-    ms = timed(torch, lambda i: B.spline_eval(t, "vgh", npos, pp[i % nb], v, g, h, NSPL,
-                                              tile=tile, stream=stream), 100, warmup)
-    return tile, ms
-
-
-def plan_time(torch, B, t, npos, batches, v, g, h, tile, stream, k, warmup):
-    plans = [B.spline_batch_plan_create([t], [npos], "vgh", [b], [v], [g], [h], [NSPL],
-                                        tile=tile, stream=stream) for b in batches]
-    ms = timed(torch, lambda i: B.spline_batch_execute(plans[i % len(plans)], stream), k, warmup)
-    ptile = B.spline_batch_plan_tile(plans[0])
-    for pl in plans:
-        B.spline_batch_plan_destroy(pl)
-    return ms, ptile
+    return best[0]
 
 
 CFG4 = [((32, 32, 32), 256, 97), ((40, 40, 40), 512, 512), ((48, 48, 48), 1152, 1500),
@@ -632,9 +651,11 @@ def batched_profile(torch, B, A, synth, args):
 
 
 def batched_extra(torch, B, A, synth, steps, warmup, keep=None):
-    """Four tables of uneven shape and batch size in one launch
-    replayed from a HIP graph, FP32 and FP16 tables.  The host coefficients
-    are left in keep["cfg4_coefs"] for the CPU leg."""
+    """Four tables of uneven shape and batch size in one launch replayed from
+    a HIP graph, FP32 and FP16 tables, each plan at its autotuned tile; the
+    two dtypes timed back to back (15 repetitions of 4 replays, rotating
+    which goes first, medians), as graph replays and as direct launches.
+    The host coefficients are left in keep["cfg4_coefs"] for the CPU leg."""
     dev = torch.device("cuda")
     stream = torch.cuda.current_stream().cuda_stream
     coefs = [synth.coef_table(*grid, n, stream=synth.table_stream(i))
@@ -651,27 +672,34 @@ def batched_extra(torch, B, A, synth, steps, warmup, keep=None):
     res = {"evals_per_replay": evals,
            "workload": "eval_vgh, tables 32^3xN=256, 40^3xN=512, 48^3xN=1152, 64^3xN=2048 "
                        "with 97/512/1500/3000 uniform positions, one launch per "
-                       "replay, 2 position sets alternated"}
-    for dt in ("f32", "f16"):
-        tabs = [B.spline_table_create(*grid, n, c, dt) for (grid, n, _), c in zip(CFG4, coefs)]
-        plans = [B.spline_batch_plan_create(tabs, npos, "vgh", pos[b], [o[0] for o in outs],
-                                            [o[1] for o in outs], [o[2] for o in outs],
-                                            [n for (_, n, _) in CFG4], stream=stream)
-                 for b in range(nb)]
-        ms = timed(torch, lambda i: B.spline_batch_execute(plans[i % nb], stream),
-                   max(50, steps // 10), warmup)
-        # the same plans issued as plain kernel launches (no graph)
-        ms_d = timed(torch, lambda i: B.spline_batch_launch(plans[i % nb], stream),
-                     max(50, steps // 10), warmup)
+                       "replay, 2 position sets alternated; FP32 and FP16 timed "
+                       "interleaved (15 reps of 4 replays, medians)"}
+    dts = ("f32", "f16")
+    tabs, plans = {}, {}
+    for dt in dts:
+        tabs[dt] = [B.spline_table_create(*grid, n, c, dt)
+                    for (grid, n, _), c in zip(CFG4, coefs)]
+        plans[dt] = [B.spline_batch_plan_create(tabs[dt], npos, "vgh", pos[b],
+                                                [o[0] for o in outs], [o[1] for o in outs],
+                                                [o[2] for o in outs], [n for (_, n, _) in CFG4],
+                                                stream=stream) for b in range(nb)]
+    ms = dict(zip(dts, map(median, interleaved(
+        torch, [lambda i, d=d: B.spline_batch_execute(plans[d][i % nb], stream) for d in dts],
+        4, reps=15))))
+    # the same plans issued as plain kernel launches (no graph)
+    ms_d = dict(zip(dts, map(median, interleaved(
+        torch, [lambda i, d=d: B.spline_batch_launch(plans[d][i % nb], stream) for d in dts],
+        4, reps=15))))
+    for dt in dts:
         alg = sum(A.batch_bytes("vgh", dt, m, n) for (_, n, m) in CFG4)
-        res[dt] = {"evals_per_s": evals / (ms * 1e-3), "us_per_replay": ms * 1e3,
-                   "hbm_gbs": alg / (ms * 1e-3) / 1e9,
-                   "direct_launch_evals_per_s": evals / (ms_d * 1e-3),
-                   "us_per_direct_launch": ms_d * 1e3,
-                   "tile": list(B.spline_batch_plan_tile(plans[0]).as_tuple())}
-        for pl in plans:
+        res[dt] = {"evals_per_s": evals / (ms[dt] * 1e-3), "us_per_replay": ms[dt] * 1e3,
+                   "hbm_gbs": alg / (ms[dt] * 1e-3) / 1e9,
+                   "direct_launch_evals_per_s": evals / (ms_d[dt] * 1e-3),
+                   "us_per_direct_launch": ms_d[dt] * 1e3,
+                   "tile": list(B.spline_batch_plan_tile(plans[dt][0]).as_tuple())}
+        for pl in plans[dt]:
             B.spline_batch_plan_destroy(pl)
-        for t in tabs:
+        for t in tabs[dt]:
             B.spline_table_destroy(t)
     res["f16_speedup_vs_f32"] = res["f16"]["evals_per_s"] / res["f32"]["evals_per_s"]
     res["f16_speedup_vs_f32_direct_launch"] = (res["f16"]["direct_launch_evals_per_s"] /
@@ -840,19 +868,23 @@ def large_extra(torch, B, A, synth, warmup):
     g = torch.empty(npos, 3, n, device=dev)
     lh = torch.empty(npos, 6, n, device=dev)
     res = {"workload": "96^3 (99^3 padded) x N=4096 table, FP32 15.9 GB / FP16 7.9 GB, "
-                       "8192 uniform positions per batch, 2 batches alternated",
+                       "8192 uniform positions per batch, 2 batches alternated; FP32 and "
+                       "FP16 of one kind timed interleaved (8 reps of 2 launches, medians)",
            "fit_interpolating": {"ms": ms_fit, "alg_bytes": fit_bytes,
                                  "hbm_gbs": fit_bytes / (ms_fit * 1e-3) / 1e9,
                                  "frac_of_peak": fit_bytes / (ms_fit * 1e-3) / 1e9 / HBM_PEAK_GBS}}
-    for dt, t in tabs.items():
-        for kind in ("vgh", "vgl"):
-            tile = B.spline_autotune(t, kind, npos)
-            ms = timed(torch, lambda i: B.spline_eval(t, kind, npos, pos[i % nb], v, g, lh, n,
-                                                      stream=stream), 20, min(warmup, 5))
+    for kind in ("vgh", "vgl"):
+        tiles = {dt: B.spline_autotune(t, kind, npos) for dt, t in tabs.items()}
+        dts = list(tabs)
+        times = interleaved(torch, [lambda i, d=d: B.spline_eval(
+            tabs[d], kind, npos, pos[i % nb], v, g, lh, n, tile=tiles[d], stream=stream)
+            for d in dts], 2, reps=8)
+        for dt, ts in zip(dts, times):
+            ms = median(ts)
             res[f"{dt}_{kind}"] = {
                 "evals_per_s": npos * n / (ms * 1e-3), "ms_per_launch": ms,
                 "hbm_gbs": A.batch_bytes(kind, dt, npos, n) / (ms * 1e-3) / 1e9,
-                "tile": list(tile.as_tuple())}
+                "tile": list(tiles[dt].as_tuple())}
     for kind in ("vgh", "vgl"):
         res[f"f16_speedup_{kind}"] = (res[f"f16_{kind}"]["evals_per_s"]
                                       / res[f"f32_{kind}"]["evals_per_s"])

@@ -79,8 +79,9 @@ __global__ void __launch_bounds__(kFitThreads) fit_axis_kernel(
 // write of HBM per element and axis instead of two of each.  Used while
 // n * 256 B fits in 64 KiB.  The LDS a line takes sets the wavefronts per
 // CU (13 at n = 48, 6 at n = 96), so longer lines keep more loads in
-// flight per wavefront: 8 up to n = 64, 32 beyond (measured on MI355X:
-// 32 loads slow the 48^3 fit by 30 % and speed the 96^3 fit by 25 %).
+// flight per wavefront: 8 up to n = 64, 16 beyond (measured on MI355X: 16
+// loads take the 96^3 fit from 22.0 to 17.4 ms; 32 or 48 gain nothing more
+// and slow the 48^3 fit).
 constexpr int kLdsMaxN = 256;
 constexpr int kLdsFewLoadsMaxN = 64;
 
@@ -152,7 +153,7 @@ bspl_status launch_fit(int nx, int ny, int nz, int64_t nspl, const float* src, f
                                    (size_t)n * 64 * sizeof(float), s, in, dst, n, inner, lines,
                                    gain, start_terms);
             else
-                hipLaunchKernelGGL(fit_axis_lds_kernel<32>, dim3((unsigned)blocks), dim3(64),
+                hipLaunchKernelGGL(fit_axis_lds_kernel<16>, dim3((unsigned)blocks), dim3(64),
                                    (size_t)n * 64 * sizeof(float), s, in, dst, n, inner, lines,
                                    gain, start_terms);
         } else {
