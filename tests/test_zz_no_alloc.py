@@ -62,6 +62,8 @@ CASES = [
     ("bf16", "v", (4, 1, 4, 0, 2, 1)),
     ("f32", "vgh", (1, 2, 1, 0, 0, 1)),   # unordered: no scratch at all
     ("f32", "vgh", (1, 2, 1, 0, 0, 4)),   # latency mode
+    ("f16", "vgh", (2, 2, 1, 0, 4, 1)),   # sorted, spline-tile-major: uses the array
+    ("f32", "vgl", (1, 2, 2, 0, 3, 1)),   # input order, spline-tile-major: no scratch
     ("f32", "vgh", None),                 # built-in default tile
 ]
 
@@ -108,10 +110,18 @@ def test_noalloc_limit_and_errors():
         assert e.value.status == B.BSPL_EUNSUPPORTED
         torch.cuda.synchronize()
         assert bool((v == 7.0).all()), "outputs written after the limit error"
-        # an unordered tile needs no scratch: the same size evaluates
-        B.spline_eval_noalloc(table, "v", npos, p, v, None, None, n, tile=(1, 1, 1, 0, 0, 1))
+        with pytest.raises(B.BsplineError) as e:  # sorted and spline-tile-major
+            B.spline_eval_noalloc(table, "v", npos, p, v, None, None, n, tile=(1, 1, 1, 0, 4, 1))
+        assert e.value.status == B.BSPL_EUNSUPPORTED
         torch.cuda.synchronize()
-        assert bool(torch.isfinite(v).all())
+        assert bool((v == 7.0).all()), "outputs written after the limit error"
+        # unsorted tiles need no scratch: the same size evaluates
+        for order in (0, 3):
+            v.fill_(7.0)
+            B.spline_eval_noalloc(table, "v", npos, p, v, None, None, n,
+                                  tile=(1, 1, 1, 0, order, 1))
+            torch.cuda.synchronize()
+            assert bool(torch.isfinite(v).all()) and not bool((v == 7.0).any())
         # exactly the limit is accepted with an ordered tile
         m = B.NOALLOC_MAX_POSITIONS
         w = torch.empty((m, n), device=dev)
