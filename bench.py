@@ -1,20 +1,27 @@
 """Benchmark: FP32 eval_vgh orbital-evals/s on the paper-scale table.
 
-Workload (one step = one eval_vgh call over one position batch): periodic
-48^3 grid (51^3 padded), N = 2048 splines, FP32 coefficients uniform in
-(-1, 1), 512 positions uniform in the unit cell per batch; 16 pre-generated
-batches are cycled so that repeated steps do not re-read the same rows
-from the Infinity Cache.  Inputs and outputs stay resident in HBM.
+Workload: periodic 48^3 grid (51^3 padded), N = 2048 splines, FP32
+coefficients uniform in (-1, 1), 512 positions uniform in the unit cell per
+batch.  One step is one eval_vgh launch on each of 16 pre-generated batches,
+so that repeated steps do not re-read the same rows from the Infinity Cache;
+an event after every step gives the mean and the median step time.  Inputs
+and outputs stay resident in HBM.
 
-Printed: one JSON line with value = VGH orbital-evals/s (npos * N / time),
-the HBM roofline of the kernel (algorithmic bytes 64*4 + 10*4 per eval),
-the FP64 oracle timed on the host cores as cpu_baseline, and extras: VGL on
-the same table, FP16/BF16 tables against FP32 at 4096 positions (with their
-deviation from the FP32-table outputs), the four-table batched workload and
-the 96^3 x 4096 tables.
+Printed: one JSON line with value = VGH orbital-evals/s (positions * N /
+time), the HBM roofline of the kernel (algorithmic bytes 64*4 + 10*4 per
+eval) against the 8 TB/s peak and the measured 86/14 streaming ceiling, the
+FP64 oracle timed on the host cores as cpu_baseline with the error of every
+output component of the FP32/FP16/BF16 tables against it, and extras: V and
+VGL, a hexagonal cell, plain against spline-blocked tables, FP16/BF16
+against FP32 at 512 and 4096 positions, the four-table batched workload,
+the fused ratios, the latency mode, the interpolating fit and the 96^3 x
+4096 tables.
 
-Modes for profiling: --profile (headline kernel only, few steps),
---copy-probe (a plain device copy of known size, to scale HBM counters).
+Modes for profiling: --profile (headline kernel only, few steps; with
+--npos/--dtype/--tile, --batched or --large for the other workloads),
+--copy-probe (a plain device copy of known size, to scale HBM counters),
+--stream-probe GIB (the 86/14 ceiling probe alone); --sweep prints the
+throughput-vs-N and tile-width study instead of the benchmark line.
 """
 
 from __future__ import annotations
@@ -183,8 +190,8 @@ def memory_ceiling(torch, B, footprints_gib=(1, 16)):
 
 
 def copy_probe(torch, nbytes=1 << 30, reps=20):
-    """Plain device-to-device copy of known size (counter calibration and the
-    measured copy bandwidth)."""
+    """Plain device-to-device copy of known size (calibration of the HBM
+    traffic counters: the bytes it reads and writes are known)."""
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     dst = torch.empty_like(src)
     ms = timed(torch, lambda i: dst.copy_(src), reps, 3)
@@ -201,6 +208,9 @@ def main(argv=None):
     ap.add_argument("--blocked", action="store_true",
                     help="profiling: a spline-blocked table instead of the plain one")
     ap.add_argument("--copy-probe", action="store_true", help="only a 1 GiB device copy")
+    ap.add_argument("--stream-probe", type=float, default=None, metavar="GIB",
+                    help="only the 86/14 streaming probe over a footprint of GIB GiB "
+                         "(six planes, 2 units per lane), 5 warm-up and 20 timed calls")
     ap.add_argument("--tile", default=None,
                     help="profiling: fixed tile vw,wx,wy,grid,order instead of the wisdom")
     ap.add_argument("--retune", action="store_true",
@@ -245,6 +255,17 @@ def main(argv=None):
     if args.copy_probe:
         gbs, ms = copy_probe(torch)
         print(json.dumps({"copy_probe_bytes": 1 << 30, "copy_ms": ms, "copy_gbs": gbs}))
+        return 0
+    if args.stream_probe is not None:
+        units = int(args.stream_probe * (1 << 30)) // 112 // 64 * 64
+        src = torch.ones(6 * units * 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty(units * 4, dtype=torch.int32, device="cuda")
+        stream = torch.cuda.current_stream().cuda_stream
+        ms = timed(torch, lambda i: B.spline_stream_probe(src, dst, units, 2, 0,
+                                                          B.BSPL_PROBE_NT_STORES, 0, stream),
+                   20, 5)
+        print(json.dumps({"stream_probe_bytes": 112 * units, "ms": ms,
+                          "gbs": 112 * units / (ms * 1e-3) / 1e9}))
         return 0
     if args.batched:
         return batched_profile(torch, B, A, synth, args)
@@ -935,31 +956,30 @@ def sweep_mode(torch, B, A, synth):
                                           "splines_per_workgroup": 64 * vw * wx,
                                           "us_per_launch": ms * 1e3,
                                           "evals_per_s": npos * n / (ms * 1e-3)}), flush=True)
-        if n <= 1024:
-            # many walker batches per launch: the 16 batches of 512 positions
-            # as one batch plan (16 entries of the same table), issued as
-            # direct launches and as a graph replay
-            outs = [(torch.empty(npos, n, device=dev), torch.empty(npos, 3, n, device=dev),
-                     torch.empty(npos, 6, n, device=dev)) for _ in range(NBATCH)]
-            plan = B.spline_batch_plan_create([t] * NBATCH, [npos] * NBATCH, "vgh", batches,
-                                              [o[0] for o in outs], [o[1] for o in outs],
-                                              [o[2] for o in outs], [n] * NBATCH,
-                                              stream=stream)
-            ms_d = timed(torch, lambda i: B.spline_batch_launch(plan, stream), 100, 10)
-            ms_g = timed(torch, lambda i: B.spline_batch_execute(plan, stream), 100, 10)
-            alg = NBATCH * A.batch_bytes("vgh", "f32", npos, n)
-            print(json.dumps({"sweep": "n_splines_batched", "grid": list(GRID), "n_splines": n,
-                              "npos": npos, "walker_batches_per_launch": NBATCH,
-                              "kernel": "eval_vgh", "us_per_launch": ms_d * 1e3,
-                              "evals_per_s": NBATCH * npos * n / (ms_d * 1e-3),
-                              "hbm_gbs": alg / (ms_d * 1e-3) / 1e9,
-                              "frac_of_peak": alg / (ms_d * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "us_per_graph_replay": ms_g * 1e3,
-                              "graph_evals_per_s": NBATCH * npos * n / (ms_g * 1e-3),
-                              "tile": list(B.spline_batch_plan_tile(plan).as_tuple())}),
-                  flush=True)
-            B.spline_batch_plan_destroy(plan)
-            del outs
+        # many walker batches per launch: the 16 batches of 512 positions
+        # as one batch plan (16 entries of the same table), issued as
+        # direct launches and as a graph replay
+        outs = [(torch.empty(npos, n, device=dev), torch.empty(npos, 3, n, device=dev),
+                 torch.empty(npos, 6, n, device=dev)) for _ in range(NBATCH)]
+        plan = B.spline_batch_plan_create([t] * NBATCH, [npos] * NBATCH, "vgh", batches,
+                                          [o[0] for o in outs], [o[1] for o in outs],
+                                          [o[2] for o in outs], [n] * NBATCH,
+                                          stream=stream)
+        ms_d = timed(torch, lambda i: B.spline_batch_launch(plan, stream), 100, 10)
+        ms_g = timed(torch, lambda i: B.spline_batch_execute(plan, stream), 100, 10)
+        alg = NBATCH * A.batch_bytes("vgh", "f32", npos, n)
+        print(json.dumps({"sweep": "n_splines_batched", "grid": list(GRID), "n_splines": n,
+                          "npos": npos, "walker_batches_per_launch": NBATCH,
+                          "kernel": "eval_vgh", "us_per_launch": ms_d * 1e3,
+                          "evals_per_s": NBATCH * npos * n / (ms_d * 1e-3),
+                          "hbm_gbs": alg / (ms_d * 1e-3) / 1e9,
+                          "frac_of_peak": alg / (ms_d * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "us_per_graph_replay": ms_g * 1e3,
+                          "graph_evals_per_s": NBATCH * npos * n / (ms_g * 1e-3),
+                          "tile": list(B.spline_batch_plan_tile(plan).as_tuple())}),
+              flush=True)
+        B.spline_batch_plan_destroy(plan)
+        del outs
         B.spline_table_destroy(t)
         # the same table stored as FP16 (per-spline scales), VGH
         coef = synth.coef_table(*GRID, n, stream=synth.table_stream(0))
@@ -972,6 +992,8 @@ def sweep_mode(torch, B, A, synth):
                           "npos": npos, "kernel": "eval_vgh", "table_dtype": "f16",
                           "us_per_launch": ms * 1e3, "evals_per_s": npos * n / (ms * 1e-3),
                           "hbm_gbs": A.batch_bytes("vgh", "f16", npos, n) / (ms * 1e-3) / 1e9,
+                          "frac_of_peak": A.batch_bytes("vgh", "f16", npos, n)
+                          / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                           "tile": list(tile.as_tuple())}), flush=True)
         B.spline_table_destroy(t16)
         del v, g, h

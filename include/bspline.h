@@ -154,9 +154,10 @@ typedef struct {
  * the rows of a tile stay in L2 while neighbouring positions re-read them
  * (order 3: positions in input order; order 4: cell-sorted and
  * XCD-grouped as order 2).  The order changes no result: every output is
- * computed the same way.  A single
- * ordered evaluation takes its permutation from hipMallocAsync on the
- * stream; for graph replay use a batch plan, which owns that memory.
+ * computed the same way.  A single cell-sorted evaluation (order 1, 2 or
+ * 4) takes its permutation from hipMallocAsync on the stream; for graph
+ * replay use a batch plan, which owns that memory, or
+ * spline_eval_noalloc.
  * split = 2 or 4 is the latency mode for a few positions (the GPU form of
  * the paper's nested threading within one walker, section "Optimizations
  * and Parallelization"): that many wavefronts share one (position, tile)
