@@ -168,37 +168,44 @@ std::vector<bspl_tile> tile_candidates(int dtype, int kind, int64_t max_nsplines
     return out;
 }
 
+// Timing events, destroyed on every return path.
+struct Events {
+    hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+    int n = 0;
+    bspl_status create(int count) {
+        for (n = 0; n < count; ++n) {
+            const hipError_t err = hipEventCreate(&e[n]);
+            if (err != hipSuccess) return hip_fail(err, "hipEventCreate");
+        }
+        return BSPL_OK;
+    }
+    ~Events() {
+        for (int i = 0; i < n; ++i) (void)hipEventDestroy(e[i]);
+    }
+};
+
 // Time `launch` (already bound to its buffers) with events: median of runs.
 template <typename F>
 static bspl_status time_launch(F&& launch, hipStream_t s, int reps, float* us) {
-    hipEvent_t a, b;
-    BSPL_HIP(hipEventCreate(&a));
-    BSPL_HIP(hipEventCreate(&b));
+    Events ev;
+    bspl_status st = ev.create(2);
+    if (st != BSPL_OK) return st;
     for (int w = 0; w < 2; ++w) {
-        bspl_status st = launch(w);
-        if (st != BSPL_OK) {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-            return st;
-        }
+        st = launch(w);
+        if (st != BSPL_OK) return st;
     }
     std::vector<float> t;
     for (int r = 0; r < reps; ++r) {
-        (void)hipEventRecord(a, s);
-        bspl_status st = launch(r);
-        (void)hipEventRecord(b, s);
-        hipError_t e = hipEventSynchronize(b);
-        if (st != BSPL_OK || e != hipSuccess) {
-            (void)hipEventDestroy(a);
-            (void)hipEventDestroy(b);
-            return st != BSPL_OK ? st : hip_fail(e, "autotune timing");
-        }
+        (void)hipEventRecord(ev.e[0], s);
+        st = launch(r);
+        (void)hipEventRecord(ev.e[1], s);
+        const hipError_t e = hipEventSynchronize(ev.e[1]);
+        if (st != BSPL_OK) return st;
+        if (e != hipSuccess) return hip_fail(e, "autotune timing");
         float ms = 0;
-        (void)hipEventElapsedTime(&ms, a, b);
+        (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
         t.push_back(ms * 1000.f);
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
     std::sort(t.begin(), t.end());
     *us = t[t.size() / 2];
     return BSPL_OK;
@@ -235,27 +242,24 @@ bspl_status sweep(const std::vector<bspl_tile>& cands, hipStream_t s,
     }
     std::sort(first.begin(), first.end());
     const size_t nf = std::min<size_t>(4, first.size());
-    hipEvent_t a, b;
-    BSPL_HIP(hipEventCreate(&a));
-    BSPL_HIP(hipEventCreate(&b));
+    Events ev;
+    bspl_status st = ev.create(2);
+    if (st != BSPL_OK) return st;
     std::vector<std::vector<float>> t(nf);
-    bspl_status st = BSPL_OK;
-    for (int r = 0; r < 25 && st == BSPL_OK; ++r) {
-        for (size_t k = 0; k < nf && st == BSPL_OK; ++k) {
+    for (int r = 0; r < 25; ++r) {
+        for (size_t k = 0; k < nf; ++k) {
             const size_t f = (k + (size_t)r) % nf;
-            (void)hipEventRecord(a, s);
+            (void)hipEventRecord(ev.e[0], s);
             st = run(ctx, cands[first[f].second], r);
-            (void)hipEventRecord(b, s);
-            const hipError_t e = hipEventSynchronize(b);
-            if (st == BSPL_OK && e != hipSuccess) st = hip_fail(e, "autotune timing");
+            (void)hipEventRecord(ev.e[1], s);
+            const hipError_t e = hipEventSynchronize(ev.e[1]);
+            if (st != BSPL_OK) return st;
+            if (e != hipSuccess) return hip_fail(e, "autotune timing");
             float ms = 0;
-            if (st == BSPL_OK) (void)hipEventElapsedTime(&ms, a, b);
+            (void)hipEventElapsedTime(&ms, ev.e[0], ev.e[1]);
             t[f].push_back(ms * 1000.f);
         }
     }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    if (st != BSPL_OK) return st;
     for (size_t f = 0; f < nf; ++f) {
         std::sort(t[f].begin(), t[f].end());
         const float us = t[f][t[f].size() / 2];
@@ -352,26 +356,25 @@ struct LayoutRace {
         bspl_status st = time_launch([&](int it) { return launches(0, 1, it); }, s, 5, &us0);
         if (st != BSPL_OK) return st;
         const int k = std::min(64, std::max(2, (int)(300.f / std::max(us0, 1.f)) + 1));
-        hipEvent_t ev[3];
-        for (int i = 0; i < 3; ++i) BSPL_HIP(hipEventCreate(&ev[i]));
+        Events ev;
+        st = ev.create(3);
+        if (st != BSPL_OK) return st;
         std::vector<float> r;
-        for (int rep = 0; rep < kLayoutReps && st == BSPL_OK; ++rep) {
+        for (int rep = 0; rep < kLayoutReps; ++rep) {
             const int first = rep & 1;
             float ms[2] = {0.f, 0.f};
-            (void)hipEventRecord(ev[0], s);
+            (void)hipEventRecord(ev.e[0], s);
             st = launches(first, k, 2 * rep);
-            (void)hipEventRecord(ev[1], s);
+            (void)hipEventRecord(ev.e[1], s);
             if (st == BSPL_OK) st = launches(1 - first, k, 2 * rep);
-            (void)hipEventRecord(ev[2], s);
-            const hipError_t e = hipEventSynchronize(ev[2]);
-            if (st == BSPL_OK && e != hipSuccess) st = hip_fail(e, "layout timing");
-            if (st != BSPL_OK) break;
-            (void)hipEventElapsedTime(&ms[first], ev[0], ev[1]);
-            (void)hipEventElapsedTime(&ms[1 - first], ev[1], ev[2]);
+            (void)hipEventRecord(ev.e[2], s);
+            const hipError_t e = hipEventSynchronize(ev.e[2]);
+            if (st != BSPL_OK) return st;
+            if (e != hipSuccess) return hip_fail(e, "layout timing");
+            (void)hipEventElapsedTime(&ms[first], ev.e[0], ev.e[1]);
+            (void)hipEventElapsedTime(&ms[1 - first], ev.e[1], ev.e[2]);
             r.push_back(ms[1] / std::max(ms[0], 1e-6f));
         }
-        for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
-        if (st != BSPL_OK) return st;
         std::sort(r.begin(), r.end());
         const float med = r[r.size() / 2];
         std::vector<float> dev;
