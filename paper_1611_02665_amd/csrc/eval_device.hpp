@@ -132,6 +132,22 @@ __device__ __forceinline__ float bcast(float x, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
+// A descriptor field as a wave-uniform (scalar-register) value.  A per-lane
+// choice among such values then becomes a select of registers; a choice
+// among the fields themselves is otherwise turned into a lane-indexed
+// vector load of kernel-argument memory, one more memory round trip at the
+// start of every work unit.
+__device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uniform_f32(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ __forceinline__ double uniform_f64(double x) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+
 // Basis weight number r (0..11) of a dimension at fraction t: r/4 selects
 // value, first or second derivative, r%4 the cell offset m.  These are the
 // uniform cubic B-spline pieces written as cubics in t (Horner form):
@@ -232,22 +248,27 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     int my_i0 = 0;
     float my_t = 0.f;
     int my_bad = 0;
-    if (lane < 3) {
-        double u;
-        if constexpr (LAT) {
+    // this lane's row of the map and axis length, selected from scalars
+    const int axis = lane < 3 ? lane : 2;
+    auto pick = [&](auto a0, auto a1, auto a2) { return axis == 0 ? a0 : (axis == 1 ? a1 : a2); };
+    const int n = pick(uniform_i32(d.ncell[0]), uniform_i32(d.ncell[1]), uniform_i32(d.ncell[2]));
+    if constexpr (LAT) {
+        const double mx = pick(uniform_f64(d.M[0][0]), uniform_f64(d.M[1][0]), uniform_f64(d.M[2][0]));
+        const double my = pick(uniform_f64(d.M[0][1]), uniform_f64(d.M[1][1]), uniform_f64(d.M[2][1]));
+        const double mz = pick(uniform_f64(d.M[0][2]), uniform_f64(d.M[1][2]), uniform_f64(d.M[2][2]));
+        if (lane < 3) {
             const double x = d.pos[p];
             const double y = d.pos[d.npos + p];
             const double z = d.pos[2 * d.npos + p];
-            const double mx = lane == 0 ? d.M[0][0] : (lane == 1 ? d.M[1][0] : d.M[2][0]);
-            const double my = lane == 0 ? d.M[0][1] : (lane == 1 ? d.M[1][1] : d.M[2][1]);
-            const double mz = lane == 0 ? d.M[0][2] : (lane == 1 ? d.M[1][2] : d.M[2][2]);
-            u = __builtin_fma(mx, x, __builtin_fma(my, y, mz * z));
-        } else {  // a box: M is diagonal
-            const double m = lane == 0 ? d.M[0][0] : (lane == 1 ? d.M[1][1] : d.M[2][2]);
-            u = d.pos[(int64_t)lane * d.npos + p] * m;
+            const double u = __builtin_fma(mx, x, __builtin_fma(my, y, mz * z));
+            my_bad = locate(u, n, my_i0, my_t) ? 0 : 1;
         }
-        const int n = lane == 0 ? d.ncell[0] : (lane == 1 ? d.ncell[1] : d.ncell[2]);
-        my_bad = locate(u, n, my_i0, my_t) ? 0 : 1;
+    } else {  // a box: M is diagonal
+        const double m = pick(uniform_f64(d.M[0][0]), uniform_f64(d.M[1][1]), uniform_f64(d.M[2][2]));
+        if (lane < 3) {
+            const double u = d.pos[(int64_t)lane * d.npos + p] * m;
+            my_bad = locate(u, n, my_i0, my_t) ? 0 : 1;
+        }
     }
     const int i0 = __builtin_amdgcn_readlane(my_i0, 0);
     const int j0 = __builtin_amdgcn_readlane(my_i0, 1);
@@ -264,7 +285,9 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
         const float t = dim == 0 ? tx : (dim == 1 ? ty : tz);
         // a box folds 1/Delta into the derivative weights; a lattice keeps
         // grid units and transforms the derivatives at the end
-        const float s = LAT ? 1.f : (dim == 0 ? d.Mf[0][0] : (dim == 1 ? d.Mf[1][1] : d.Mf[2][2]));
+        const float s = LAT ? 1.f
+                            : (dim == 0 ? uniform_f32(d.Mf[0][0])
+                                        : (dim == 1 ? uniform_f32(d.Mf[1][1]) : uniform_f32(d.Mf[2][2])));
         wv = basis_weight(r, t);
         wv *= r >= 8 ? s * s : (r >= 4 ? s : 1.f);
         if (bad) wv = __builtin_nanf("");
@@ -318,6 +341,12 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
 #pragma unroll
         for (int k = 0; k < 4; ++k) ring[slot][k] = RowT::load(base + (go + (uint32_t)k * d.row_bytes));
     };
+    // per-spline scales of reduced-precision tables, loaded while the last
+    // row groups are still in flight
+    float sc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) sc[e] = 1.f;
+    constexpr int kScaleGroup = NG > DEPTH ? NG - DEPTH : 0;
 
     float acc[NOUT][VW];
 #pragma unroll
@@ -332,6 +361,12 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
         if (g + DEPTH - 1 < NG) issue(g + DEPTH - 1, (g + DEPTH - 1) % DEPTH);
+        if constexpr (EB == 2) {
+            if (g == kScaleGroup && valid > 0) {
+#pragma unroll
+                for (int e = 0; e < VW; ++e) sc[e] = d.scales[n0 + e];
+            }
+        }
         const int i = g >> 2, j = g & 3;
         if (j == 0) {
 #pragma unroll
@@ -344,17 +379,20 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
         for (int k = 0; k < 4; ++k) RowT::widen(ring[g % DEPTH][k], q[k]);
 #pragma unroll
         for (int e = 0; e < VW; ++e) {
-            float s0 = az[0] * q[0][e];
+            // the first products are FMAs with a zero addend: with 16-bit
+            // tables they take the half directly (v_fma_mix_f32) instead of
+            // after a separate conversion
+            float s0 = fmaf(az[0], q[0][e], 0.f);
             s0 = fmaf(az[1], q[1][e], s0);
             s0 = fmaf(az[2], q[2][e], s0);
             s0 = fmaf(az[3], q[3][e], s0);
             Y[0][e] = fmaf(ay[j], s0, Y[0][e]);
             if constexpr (KI != BSPL_V) {
-                float s1 = daz[0] * q[0][e];
+                float s1 = fmaf(daz[0], q[0][e], 0.f);
                 s1 = fmaf(daz[1], q[1][e], s1);
                 s1 = fmaf(daz[2], q[2][e], s1);
                 s1 = fmaf(daz[3], q[3][e], s1);
-                float s2 = d2az[0] * q[0][e];
+                float s2 = fmaf(d2az[0], q[0][e], 0.f);
                 s2 = fmaf(d2az[1], q[1][e], s2);
                 s2 = fmaf(d2az[2], q[2][e], s2);
                 s2 = fmaf(d2az[3], q[3][e], s2);
@@ -463,9 +501,6 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     valid_out = valid;
     if (valid <= 0) return;
     if constexpr (Elem<T>::bytes == 2) {
-        float sc[VW];
-#pragma unroll
-        for (int e = 0; e < VW; ++e) sc[e] = d.scales[n0 + e];
 #pragma unroll
         for (int o = 0; o < NO; ++o)
 #pragma unroll
