@@ -5,8 +5,8 @@
 // consecutive splines.  Lane l owns splines [tile*64*VW + l*VW, +VW).
 //  1. Lanes 0..2 place the position in its cell, one dimension each, in FP64
 //     (periodic wrap, lower-bound index, fraction t rounded to FP32).
-//  2. Lanes 0..35 each form one of the 36 basis weights (value, first and
-//     second derivative, 4 per dimension, derivatives already scaled by
+//  2. Lane d < 3 forms the 12 basis weights of dimension d (value, first and
+//     second derivative of 4 cell offsets, derivatives already scaled by
 //     1/Delta and 1/Delta^2); v_readlane broadcasts them into scalar
 //     registers, so every lane of the wavefront shares them for free.
 //  3. For each of the 16 (i,j) pairs the 4 z-consecutive rows of the tile
@@ -132,22 +132,6 @@ __device__ __forceinline__ float bcast(float x, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
-// A descriptor field as a wave-uniform (scalar-register) value.  A per-lane
-// choice among such values then becomes a select of registers; a choice
-// among the fields themselves is otherwise turned into a lane-indexed
-// vector load of kernel-argument memory, one more memory round trip at the
-// start of every work unit.
-__device__ __forceinline__ int uniform_i32(int x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ __forceinline__ float uniform_f32(float x) {
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
-}
-__device__ __forceinline__ double uniform_f64(double x) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b);
-    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32));
-    return __builtin_bit_cast(double, (hi << 32) | lo);
-}
-
 // Basis weight number r (0..11) of a dimension at fraction t: r/4 selects
 // value, first or second derivative, r%4 the cell offset m.  These are the
 // uniform cubic B-spline pieces written as cubics in t (Horner form):
@@ -171,27 +155,23 @@ __device__ __forceinline__ float basis_weight(int r, float t) {
     return ((c3 * t + c2) * t + c1) * t + c0;
 }
 
-// Cell location of one grid coordinate u (FP64).  Returns false for a
-// non-finite input.  A position with no fraction bits left (|u| >= 2^50) is
-// placed on grid point 0.
-__device__ __forceinline__ bool locate(double u, int n, int& i0, float& t) {
-    if (!__builtin_isfinite(u)) {
-        i0 = 0;
-        t = 0.f;
-        return false;
-    }
-    const double nd = (double)n;
-    double w = 0.0;
-    if (__builtin_fabs(u) < 1125899906842624.0) {
-        w = u - nd * __builtin_floor(u / nd);
-        if (w < 0.0) w += nd;
-        if (w >= nd) w = 0.0;  // rounded up to n: the image of 0
-    }
+// Cell location of one grid coordinate u (FP64) on an axis of nd cells.
+// Returns false for a non-finite input.  A position with no fraction bits
+// left (|u| >= 2^50), and a non-finite one, is placed on grid point 0.  The
+// steps are selects, not branches, so that the loads feeding them (the
+// position and the axis row) issue together and are waited for once.
+__device__ __forceinline__ bool locate(double u, double nd, int& i0, float& t) {
+    const bool finite = __builtin_isfinite(u);
+    const double v = __builtin_fabs(u) < 1125899906842624.0 ? u : 0.0;
+    double w = v - nd * __builtin_floor(v / nd);
+    w = w < 0.0 ? w + nd : w;
+    w = w >= nd ? 0.0 : w;  // rounded up to n: the image of 0
+    const int n = (int)nd;
     int i = (int)__builtin_floor(w);
     i = i < 0 ? 0 : (i > n - 1 ? n - 1 : i);
     i0 = i;
     t = (float)(w - (double)i);
-    return true;
+    return finite;
 }
 
 template <int KIND> struct Shape;
@@ -215,8 +195,8 @@ __device__ __forceinline__ int sym_col(int k) { return k < 3 ? k : (k < 5 ? k - 
 // it out of private memory.
 __device__ __forceinline__ float hess_coef(const TableDesc& d, int k, int q) {
     const int a = sym_row(k), b = sym_col(k), dd = sym_row(q), e = sym_col(q);
-    float c = d.Mf[dd][a] * d.Mf[e][b];
-    if (dd != e) c = fmaf(d.Mf[e][a], d.Mf[dd][b], c);
+    float c = (float)d.axis[dd][a] * (float)d.axis[e][b];
+    if (dd != e) c = fmaf((float)d.axis[e][a], (float)d.axis[dd][b], c);
     return c;
 }
 
@@ -248,27 +228,22 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     int my_i0 = 0;
     float my_t = 0.f;
     int my_bad = 0;
-    // this lane's row of the map and axis length, selected from scalars
-    const int axis = lane < 3 ? lane : 2;
-    auto pick = [&](auto a0, auto a1, auto a2) { return axis == 0 ? a0 : (axis == 1 ? a1 : a2); };
-    const int n = pick(uniform_i32(d.ncell[0]), uniform_i32(d.ncell[1]), uniform_i32(d.ncell[2]));
-    if constexpr (LAT) {
-        const double mx = pick(uniform_f64(d.M[0][0]), uniform_f64(d.M[1][0]), uniform_f64(d.M[2][0]));
-        const double my = pick(uniform_f64(d.M[0][1]), uniform_f64(d.M[1][1]), uniform_f64(d.M[2][1]));
-        const double mz = pick(uniform_f64(d.M[0][2]), uniform_f64(d.M[1][2]), uniform_f64(d.M[2][2]));
-        if (lane < 3) {
+    float my_scale = 1.f;  // lane d < 3 of a box: n_d / L_d in FP32
+    if (lane < 3) {
+        // the lane's map row and cell count (one lane-indexed read of the
+        // descriptor) and the position, all issued before the first wait
+        const double* row = d.axis[lane];
+        double u;
+        if constexpr (LAT) {
             const double x = d.pos[p];
             const double y = d.pos[d.npos + p];
             const double z = d.pos[2 * d.npos + p];
-            const double u = __builtin_fma(mx, x, __builtin_fma(my, y, mz * z));
-            my_bad = locate(u, n, my_i0, my_t) ? 0 : 1;
+            u = __builtin_fma(row[0], x, __builtin_fma(row[1], y, row[2] * z));
+        } else {  // a box: the map is diagonal
+            u = d.pos[(int64_t)lane * d.npos + p] * row[lane];
+            my_scale = (float)row[lane];
         }
-    } else {  // a box: M is diagonal
-        const double m = pick(uniform_f64(d.M[0][0]), uniform_f64(d.M[1][1]), uniform_f64(d.M[2][2]));
-        if (lane < 3) {
-            const double u = d.pos[(int64_t)lane * d.npos + p] * m;
-            my_bad = locate(u, n, my_i0, my_t) ? 0 : 1;
-        }
+        my_bad = locate(u, row[3], my_i0, my_t) ? 0 : 1;
     }
     const int i0 = __builtin_amdgcn_readlane(my_i0, 0);
     const int j0 = __builtin_amdgcn_readlane(my_i0, 1);
@@ -276,38 +251,52 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     const int bad = __builtin_amdgcn_readlane(my_bad, 0) | __builtin_amdgcn_readlane(my_bad, 1) |
                     __builtin_amdgcn_readlane(my_bad, 2);
 
-    // 2. weights: lane 12*dim + r computes weight r of that dimension
-    float wv;
-    {
-        const float tx = bcast(my_t, 0), ty = bcast(my_t, 1), tz = bcast(my_t, 2);
-        const int dim = lane >= 24 ? 2 : (lane >= 12 ? 1 : 0);
-        const int r = lane - 12 * dim;
-        const float t = dim == 0 ? tx : (dim == 1 ? ty : tz);
-        // a box folds 1/Delta into the derivative weights; a lattice keeps
-        // grid units and transforms the derivatives at the end
-        const float s = LAT ? 1.f
-                            : (dim == 0 ? uniform_f32(d.Mf[0][0])
-                                        : (dim == 1 ? uniform_f32(d.Mf[1][1]) : uniform_f32(d.Mf[2][2])));
-        wv = basis_weight(r, t);
-        wv *= r >= 8 ? s * s : (r >= 4 ? s : 1.f);
-        if (bad) wv = __builtin_nanf("");
-    }
+    // 2. weights: lane d < 3 evaluates the 12 weights of axis d (value,
+    //    first and second derivative of the 4 cell offsets) in straight-line
+    //    code; a box folds 1/Delta_d into the derivative weights, a lattice
+    //    keeps grid units and transforms the derivatives at the end.
+    //    v_readlane then moves them into scalar registers, so every lane of
+    //    the wavefront shares them at no VGPR cost.
     float ax[4], dax[4], d2ax[4], ay[4], day[4], d2ay[4], az[4], daz[4], d2az[4];
+    auto form_weights = [&]() {
+        float w[12];
+        const float s = my_scale;
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        // x weights of this unit's slabs (islab is 0 unless the unit is split)
-        ax[m] = bcast(wv, islab + m);
-        ay[m] = bcast(wv, 12 + m);
-        az[m] = bcast(wv, 24 + m);
-        if constexpr (KI != BSPL_V) {
-            dax[m] = bcast(wv, 4 + islab + m);
-            d2ax[m] = bcast(wv, 8 + islab + m);
-            day[m] = bcast(wv, 16 + m);
-            d2ay[m] = bcast(wv, 20 + m);
-            daz[m] = bcast(wv, 28 + m);
-            d2az[m] = bcast(wv, 32 + m);
+        for (int r = 0; r < 12; ++r) {
+            w[r] = basis_weight(r, my_t);
+            w[r] *= r >= 8 ? s * s : (r >= 4 ? s : 1.f);
+            if (bad) w[r] = __builtin_nanf("");
         }
-    }
+        // weight r of axis d; x weights are those of this unit's slabs
+        // (islab is 0 unless the unit is split, and wave-uniform)
+        auto wt = [&](int d_axis, int r) { return bcast(w[r], d_axis); };
+        auto wx = [&](int r0, int m) {
+            float v = wt(0, r0 + m);
+            if constexpr (NG < 16) {
+#pragma unroll
+                for (int k = 1; k < 4; ++k)
+                    if (m + k < 4 && islab == k) v = wt(0, r0 + m + k);
+            }
+            return v;
+        };
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            ax[m] = wx(0, m);
+            ay[m] = wt(1, m);
+            az[m] = wt(2, m);
+            if constexpr (KI != BSPL_V) {
+                dax[m] = wx(4, m);
+                d2ax[m] = wx(8, m);
+                day[m] = wt(1, 4 + m);
+                d2ay[m] = wt(1, 8 + m);
+                daz[m] = wt(2, 4 + m);
+                d2az[m] = wt(2, 8 + m);
+            }
+        }
+    };
+
+    constexpr bool kIssueFirst = VW * EB <= 8;
+    if constexpr (!kIssueFirst) form_weights();
 
     // 3. gather and reduce
     const int n0 = chunk * (64 * VW) + lane * VW;
@@ -355,8 +344,16 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
         for (int e = 0; e < VW; ++e) acc[o][e] = 0.f;
     float Y[NY][VW];
 
+    // The first DEPTH-1 row groups go out before the weights are formed, so
+    // that the weights' arithmetic overlaps their flight (one position:
+    // 3.99 against 4.17 us per evaluation).  With 16-byte loads per lane
+    // (FP32 at VW=4, 16-bit tables at VW=8) the compiler then schedules the
+    // ring as single loads with full waits between them (the dense FP32
+    // launch: 299 against 273 us), so those tiles form the weights before
+    // the gather set-up.
 #pragma unroll
     for (int g = 0; g < DEPTH - 1; ++g) issue(g, g);
+    if constexpr (kIssueFirst) form_weights();
 
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
@@ -451,7 +448,7 @@ __device__ __forceinline__ void eval_core(const TableDesc& d, int p, int chunk, 
     if constexpr (LAT && KIND != BSPL_V) {
         float m[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) m[k] = d.Mf[k / 3][k % 3];
+        for (int k = 0; k < 9; ++k) m[k] = (float)d.axis[k / 3][k % 3];
         // lane 6k + q holds the coefficient of H_u component q in H_r component k
         float hc = 0.f;
         if (lane < 36) hc = hess_coef(d, lane / 6, lane % 6);

@@ -67,10 +67,11 @@ struct TableDesc {
     int64_t npos;
     int64_t ldo;
     int64_t groups_begin;     // first workgroup-block index of this table
-    double M[3][3];           // grid coordinates u_d = sum_a M[d][a] r_a (box: n_d/L_d diagonal)
-    float Mf[3][3];           // the same in FP32, for derivative weights and transforms
-    int32_t lattice;          // 1: derivatives in grid units, then transformed by Mf
-    int32_t ncell[3];
+    // Row d: the grid map's row, u_d = sum_a axis[d][a] r_a (a box: n_d/L_d on
+    // the diagonal), then the cell count n_d (as a double).  Lane d of a
+    // wavefront reads its row with one 32-byte load alongside the position.
+    double axis[3][4];
+    int32_t lattice;          // 1: derivatives in grid units, then transformed by the map
     uint32_t row_bytes;       // bytes between consecutive z rows
     uint32_t ystride;         // bytes between consecutive y planes
     uint32_t xstride;         // bytes between consecutive x planes

@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(kOrderThreads) order_tables_kernel(const Order
 static OrderMap fraction_map(const TableDesc& d) {
     OrderMap m;
     for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) m.f[a][b] = d.M[a][b] / (double)d.ncell[a];
+        for (int b = 0; b < 3; ++b) m.f[a][b] = d.axis[a][b] / d.axis[a][3];
     return m;
 }
 

@@ -162,12 +162,10 @@ bspl_status make_desc(const bspl_table* t, int64_t npos, const double* pos, floa
     d.ldo = ldo;
     d.groups_begin = 0;
     const int ncell[3] = {in.nx, in.ny, in.nz};
-    for (int k = 0; k < 3; ++k) d.ncell[k] = ncell[k];
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-            d.M[a][b] = t->grid_map[a][b];
-            d.Mf[a][b] = (float)t->grid_map[a][b];
-        }
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) d.axis[a][b] = t->grid_map[a][b];
+        d.axis[a][3] = (double)ncell[a];
+    }
     d.lattice = t->lattice;
     d.row_bytes = (uint32_t)in.row_bytes;
     d.ystride = (uint32_t)((int64_t)in.pz * in.row_bytes);
