@@ -890,7 +890,7 @@ def large_extra(torch, B, A, synth, warmup):
     lh = torch.empty(npos, 6, n, device=dev)
     res = {"workload": "96^3 (99^3 padded) x N=4096 table, FP32 15.9 GB / FP16 7.9 GB, "
                        "8192 uniform positions per batch, 2 batches alternated; FP32 and "
-                       "FP16 of one kind timed interleaved (8 reps of 2 launches, medians)",
+                       "FP16 of one kind timed interleaved (10 reps of 6 launches, medians)",
            "fit_interpolating": {"ms": ms_fit, "alg_bytes": fit_bytes,
                                  "hbm_gbs": fit_bytes / (ms_fit * 1e-3) / 1e9,
                                  "frac_of_peak": fit_bytes / (ms_fit * 1e-3) / 1e9 / HBM_PEAK_GBS}}
@@ -899,7 +899,7 @@ def large_extra(torch, B, A, synth, warmup):
         dts = list(tabs)
         times = interleaved(torch, [lambda i, d=d: B.spline_eval(
             tabs[d], kind, npos, pos[i % nb], v, g, lh, n, tile=tiles[d], stream=stream)
-            for d in dts], 2, reps=8)
+            for d in dts], 6, reps=10)
         for dt, ts in zip(dts, times):
             ms = median(ts)
             res[f"{dt}_{kind}"] = {
