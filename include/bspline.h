@@ -65,7 +65,7 @@ typedef enum {
     BSPL_EINVAL = 1,       /* bad argument: NULL, non-positive size, bad enum */
     BSPL_ENOMEM = 2,       /* device or host allocation failed */
     BSPL_EDEVICE = 3,      /* a HIP call failed; see spline_last_error() */
-    BSPL_EUNSUPPORTED = 4, /* valid request this build does not support */
+    BSPL_EUNSUPPORTED = 4, /* valid request the library does not support */
     BSPL_EIO = 5,          /* wisdom file could not be read or written */
     BSPL_STATUS_ENUM_MIN = -2147483647 - 1,
     BSPL_STATUS_ENUM_MAX = 2147483647
