@@ -46,7 +46,7 @@ def _random_case(rng):
     return dims, n, dtype, kind, cell, tile, npos
 
 
-@pytest.mark.parametrize("case", range(150))
+@pytest.mark.parametrize("case", range(600))
 def test_random_configuration(case):
     rng = np.random.default_rng(1000 + case)
     dims, n, dtype, kind, cell, tile, npos = _random_case(rng)
@@ -80,7 +80,7 @@ def _random_cell(rng):
             return cell
 
 
-@pytest.mark.parametrize("case", range(40))
+@pytest.mark.parametrize("case", range(120))
 def test_random_plan(case):
     """A batch plan over 1-5 random tables (some empty), replayed twice."""
     rng = np.random.default_rng(5000 + case)
@@ -146,7 +146,7 @@ def test_random_plan(case):
             B.spline_table_destroy(t)
 
 
-@pytest.mark.parametrize("case", range(30))
+@pytest.mark.parametrize("case", range(90))
 def test_random_ratio(case):
     rng = np.random.default_rng(9000 + case)
     dims = tuple(int(x) for x in rng.integers(1, 9, 3))
